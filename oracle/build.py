@@ -1,0 +1,26 @@
+"""Build the oracle's shared library (plain C, gcc, OpenMP).
+
+Test infrastructure: the product library never builds against or loads it.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ftlm_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(force=True):
+    """Compile liboracle.so next to its source; returns the library path."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())
