@@ -1,0 +1,247 @@
+/*
+ * ftlm.h - C ABI of libftlm: the data-parallel hot path of the
+ * finite-temperature Lanczos method (FTLM) for spin-1/2 Heisenberg clusters
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Citations refer to arXiv 2605.26261, "GPU-accelerated finite-temperature
+ * Lanczos method for spin Hamiltonians" (Sec. = section, Eq. = equation,
+ * Alg. = algorithm).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status.   Every int-returning function returns FTLM_OK (0) or a negative
+ *           FTLM_E_* code; ftlm_last_error() then returns a thread-local
+ *           message. No C++ exception crosses this boundary.
+ * Labels.   A basis state of N sites is the integer n whose bit k is 1 when
+ *           site k is up (Eq. 11 at s = 1/2: a_k = m_k + 1/2). The sector with
+ *           n_up up spins has total S^z = M = n_up - N/2 (Eq. 17) and
+ *           dimension D = C(N, n_up) (Eq. 15 at s = 1/2); its basis is ordered
+ *           by increasing label (the ordering behind Eq. 18).
+ * Indices.  Labels and sector indices are uint64_t at this boundary. The
+ *           index of a label outside the sector is FTLM_NONE (the -1 of
+ *           Alg. 2). Kernels hold indices as uint32, so D must be < 2^32.
+ * Memory.   Device buffers are owned by the caller (for example torch
+ *           tensors on "cuda") and passed as raw device pointers; sizes come
+ *           from the *_bytes() queries. These entry points never allocate
+ *           device memory. Handles (ftlm_graph, ftlm_sector, ftlm_plan,
+ *           ftlm_server) are host objects owned by the library, with
+ *           create/destroy pairs; a handle must not outlive the device
+ *           buffers it references. Handles are not thread-safe.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *           stream). Device work is enqueued in stream order and returns
+ *           before it completes, unless the function returns host data, in
+ *           which case it synchronizes the stream first.
+ * Vectors.  A block of B vectors of a sector is stored row-major as [D][B]
+ *           (row t holds component t of every vector), so one partner index
+ *           serves all B vectors (Sec. 2, batched Lanczos). Element type is
+ *           FTLM_F32 (float) or FTLM_F64 (double).
+ */
+#ifndef FTLM_H
+#define FTLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FTLM_OK 0
+#define FTLM_E_INVALID (-1)  /* a bad argument (null pointer, bad code, bad graph) */
+#define FTLM_E_RANGE (-2)    /* a size outside what the library supports */
+#define FTLM_E_NOSPACE (-3)  /* a caller buffer smaller than the size query */
+#define FTLM_E_DEVICE (-4)   /* a HIP runtime error; the message names it */
+#define FTLM_E_AGAIN (-5)    /* server: the result is not ready yet */
+#define FTLM_E_REJECTED (-6) /* server: the request can never fit the arena */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define FTLM_CLT 0   /* compressed lookup table indexing (Sec. 2, Eqs. 18-21, Alg. 2) */
+#define FTLM_CR 1    /* combinatorial ranking, no per-label table (Sec. 2, Eqs. 15-17, Alg. 1) */
+
+#define FTLM_F32 0
+#define FTLM_F64 1
+
+#define FTLM_PM1 0   /* i.i.d. +-1 entries */
+#define FTLM_GAUSS 1 /* i.i.d. standard normal entries */
+#define FTLM_UNIT 2  /* the unit vector e_r (exact trace when R = D) */
+
+#define FTLM_NONE UINT64_MAX
+
+typedef struct ftlm_graph ftlm_graph;
+typedef struct ftlm_sector ftlm_sector;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* ftlm_last_error(void);
+
+/* ABI version of this header. */
+int ftlm_version(void);
+
+/* ---- cluster graph ------------------------------------------------------
+ * ftlm_graph_create: the Heisenberg model of Eq. (1) on N sites with one
+ * coupling per bond, H = sum_b J_b s_i . s_j (the bond-dependent couplings
+ * the outlook of Sec. 4 names). bi, bj, J are host arrays of n_bonds entries;
+ * each bond needs 0 <= i, j < N and i != j; (i, j) and (j, i) are the same
+ * bond, and repeated bonds are merged by summing their J. 2 <= N <= 64,
+ * 1 <= n_bonds <= 128. The arrays are copied; *out receives the handle.
+ * Errors: FTLM_E_INVALID for a null pointer or a bad site, FTLM_E_RANGE for
+ * N or n_bonds out of range. */
+int ftlm_graph_create(int n_sites, int n_bonds, const int32_t* bi, const int32_t* bj,
+                      const double* J, ftlm_graph** out);
+void ftlm_graph_destroy(ftlm_graph* g);
+int ftlm_graph_n_sites(const ftlm_graph* g);
+int ftlm_graph_n_bonds(const ftlm_graph* g);
+
+/* ---- S^z sector -------------------------------------------------------
+ * ftlm_sector_table_bytes: device bytes the sector tables need. Both modes
+ * hold a binomial table C(p, k) (the cumulative dimension table D_c(p, A, 1)
+ * of Eq. 16 at s = 1/2, a few KB). FTLM_CLT adds the sorted basis (uint32
+ * per state, N <= 32) and the compressed lookup table: one {mask, prefix}
+ * pair of uint32 per block of 32 labels over [0, 2^N) (Eqs. 18-21; 8 bytes
+ * per block, Eq. 21). FTLM_CR stores nothing per label (Sec. 2, CR).
+ * Errors: FTLM_E_RANGE when N > 64, D >= 2^32, or N > 32 in FTLM_CLT mode. */
+int ftlm_sector_table_bytes(int n_sites, int n_up, int mode, size_t* bytes);
+
+/* ftlm_sector_create: builds the tables into the caller's device buffer
+ * table_dev (at least ftlm_sector_table_bytes bytes, 256-byte aligned) on
+ * `stream`: the binomial table, and in FTLM_CLT mode the basis (one unrank
+ * per state) and the lookup table (the occupancy mask of each block and the
+ * count of sector labels below it, Eq. 18). The build is asynchronous; the
+ * handle may be used on the same stream at once. FTLM_E_NOSPACE if bytes is
+ * too small. */
+int ftlm_sector_create(int n_sites, int n_up, int mode, void* table_dev, size_t bytes,
+                       void* stream, ftlm_sector** out);
+uint64_t ftlm_sector_dim(const ftlm_sector* s);
+int ftlm_sector_mode(const ftlm_sector* s);
+void ftlm_sector_destroy(ftlm_sector* s);
+
+/* ftlm_rank: idx_dev[i] = sector index of labels_dev[i], FTLM_NONE when the
+ * label is not in the sector. Mode FTLM_CLT looks up the table (Alg. 2);
+ * mode FTLM_CR ranks digit by digit over the binomial table (Alg. 1). Both
+ * arrays are device uint64[n]. */
+int ftlm_rank(const ftlm_sector* s, const uint64_t* labels_dev, uint64_t* idx_dev, uint64_t n,
+              void* stream);
+
+/* ftlm_unrank: labels_dev[i] = label of sector index idx_dev[i] (FTLM_NONE
+ * for an index >= D). FTLM_CLT reads the stored basis; FTLM_CR runs the
+ * inverse of Alg. 1 (each digit chosen by comparing the remaining rank with
+ * the cumulative counts, Sec. 2). Device uint64[n] arrays. */
+int ftlm_unrank(const ftlm_sector* s, const uint64_t* idx_dev, uint64_t* labels_dev, uint64_t n,
+                void* stream);
+
+/* ftlm_clt_export: copies the lookup table's masks and prefix counts of
+ * blocks [0, nblocks) to host arrays (test hook; FTLM_CLT mode only;
+ * synchronizes the stream). nblocks may not exceed the table's block count
+ * max(1, 2^N / 32). */
+int ftlm_clt_export(const ftlm_sector* s, uint32_t* mask_host, uint32_t* prefix_host,
+                    uint64_t nblocks, void* stream);
+
+/* ftlm_neighbors: for rows t0..t0+count-1 and each bond b of the graph (the
+ * merged bonds in order of first appearance, n_bonds = ftlm_graph_n_bonds),
+ * idx_dev[(t - t0) * n_bonds + b] = the sector index
+ * of the partner label n_t XOR (2^i + 2^j) when sites i, j of bond b are
+ * antiparallel in n_t, else FTLM_NONE (Eq. 12 at s = 1/2; Eqs. 13-14 give the
+ * coefficient J_b / 2). The indices come from the same code the H.x kernels
+ * use. idx_dev is device uint64[count * n_bonds]. Test hook. */
+int ftlm_neighbors(const ftlm_sector* s, const ftlm_graph* g, uint64_t t0, uint64_t count,
+                   uint64_t* idx_dev, void* stream);
+
+/* ---- matrix-free H.x (Eq. 12) -------------------------------------------
+ * y = H x for a block of nvec vectors in the [D][nvec] layout, in the
+ * row-wise gather form of Sec. 2: each output row t is computed from its own
+ * state n_t as
+ *   y[t] = sum_b J_b s^z_i s^z_j x[t] + sum_{b antiparallel} (J_b / 2) x[idx(n_t ^ mask_b)]
+ * with s^z_i s^z_j = +-1/4, no atomics. dtype FTLM_F32 accumulates each row in
+ * FP32, FTLM_F64 in FP64. x and y must not overlap. 1 <= nvec <= 64. */
+int ftlm_hv(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, void* y_dev, int nvec,
+            int dtype, void* stream);
+
+/* ftlm_hv_rows: the rows [row0, row0 + nrows) of H x only (one device's share
+ * of a row-partitioned product). x_dev holds all D rows; y_dev holds nrows
+ * rows (row row0 + r at position r). */
+int ftlm_hv_rows(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, void* y_dev,
+                 int nvec, int dtype, uint64_t row0, uint64_t nrows, void* stream);
+
+/* ---- start vectors --------------------------------------------------------
+ * ftlm_start_vectors: writes R random vectors [D][R] of the given dtype into
+ * q_dev, unnormalized, and their FP64 norms into norms_host[R] (synchronizes).
+ * Vector r (0 <= r < R) is sample r0 + r, drawn from the counter-based
+ * SplitMix64 generator (Steele, Lea, Flood 2014) keyed by (seed, n_up,
+ * r0 + r): entry i uses outputs numbered from i, so a vector never depends on
+ * R. FTLM_PM1 takes the sign from the top bit of output i; FTLM_GAUSS applies
+ * Box-Muller to 53-bit uniforms from outputs 2i and 2i + 1; FTLM_UNIT is
+ * e_{r0+r}. The paper draws normalized random vectors (Sec. 2, FTLM) with the
+ * same seeds in every precision (Sec. 3.1). work_dev/work_bytes: scratch of
+ * at least ftlm_lanczos_workspace_bytes(s, R, dtype) bytes. */
+int ftlm_start_vectors(const ftlm_sector* s, uint64_t seed, uint64_t r0, int R, int dist,
+                       int dtype, void* q_dev, double* norms_host, void* work_dev,
+                       size_t work_bytes, void* stream);
+
+/* ---- Lanczos ----------------------------------------------------------------
+ * ftlm_lanczos_workspace_bytes: device scratch for R chains of the sector. */
+int ftlm_lanczos_workspace_bytes(const ftlm_sector* s, int R, int dtype, size_t* bytes);
+
+/* ftlm_lanczos: R Lanczos chains without reorthogonalization (Sec. 2, the
+ * paragraph after Eq. 3), all R advanced together by one multi-vector H.x
+ * per step, started from the normalized vectors of ftlm_start_vectors. Step
+ * k (Paige's ordering, FP64 reductions):
+ *   w = H q_k - beta_{k-1} q_{k-1};  alpha_k = <q_k, w>;  w -= alpha_k q_k;
+ *   beta_k = |w|;  q_{k+1} = w / beta_k.
+ * Vectors are stored in dtype; alpha, beta and the norms are accumulated in
+ * FP64 with a fixed reduction order (the result does not depend on which
+ * other chains share the batch). Chain r stops after step k when k reaches
+ * min(M, D) or beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}), with eps =
+ * 1e-6 (FP32) or 1e-12 (FP64). Outputs (host, synchronizes): alpha_host and
+ * beta_host [R][M] (row r holds chain r; entries past steps_host[r] are 0),
+ * steps_host[R]. 1 <= R <= 64, 1 <= M <= 4096. */
+int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint64_t r0, int R,
+                 int M, int dist, int dtype, void* work_dev, size_t work_bytes, double* alpha_host,
+                 double* beta_host, int32_t* steps_host, void* stream);
+
+/* ---- Ritz values and the thermal reduction (host, FP64) --------------------
+ * ftlm_ritz: eigenvalues theta[m] (ascending) of the m x m symmetric
+ * tridiagonal T with diagonal alpha[0..m-1] and off-diagonal beta[0..m-2],
+ * and the weights weight[k] = s_{k,1}^2, the squared first components of its
+ * normalized eigenvectors (Sec. 2; they sum to 1). Implicit QL with
+ * Wilkinson shifts, FP64, on the host (Sec. 2: the tridiagonal problem is
+ * solved on the host in FP64). */
+int ftlm_ritz(int m, const double* alpha, const double* beta, double* theta, double* weight);
+
+/* One sector's Lanczos samples for ftlm_thermo. theta and weight are
+ * [R][stride] host arrays; sample r uses its first steps[r] entries. */
+typedef struct ftlm_sector_result {
+    int32_t n_up;
+    int32_t R;
+    int32_t stride;
+    int32_t reserved;
+    uint64_t dim;        /* D_Gamma */
+    double mult;         /* 1 for M = 0, 2 for M > 0 (sectors -M mirror +M, Sec. 2) */
+    const double* theta;
+    const double* weight;
+    const int32_t* steps;
+} ftlm_sector_result;
+
+/* ftlm_thermo: the FTLM thermal reduction over n_sectors sectors at nT
+ * temperatures T[] (k_B = 1): Eqs. (6)-(8) with prefactor mult * D / R per
+ * sector, every Boltzmann factor shifted by E0 = the smallest Ritz value
+ * over all samples (the shift cancels in every ratio), C = beta^2 (<H^2> -
+ * <H>^2), chi = g^2 beta sum_M M^2 Z_M / sum_M Z_M (Eq. 9). Writes E, C, chi
+ * and lnZ = ln Z (with the shift undone) as host arrays of nT entries; any
+ * output pointer may be NULL. */
+int ftlm_thermo(int n_sites, int n_sectors, const ftlm_sector_result* sectors, int nT,
+                const double* T, double g, double* E, double* C, double* chi, double* lnZ);
+
+/* ---- measurement hooks ---------------------------------------------------
+ * When enabled, the library records a pair of HIP events around every H.x
+ * launch on the launch's own stream and accumulates their elapsed times;
+ * ftlm_stats_read synchronizes on the recorded events and reports the count
+ * of H.x launches and their total milliseconds since the last reset. */
+int ftlm_stats_enable(int on);
+int ftlm_stats_reset(void);
+int ftlm_stats_read(int64_t* hv_launches, double* hv_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTLM_H */

@@ -68,12 +68,18 @@ def lib():
         L.orc_unrank_many.argtypes = [i32, i32, vp, u64, vp]
         L.orc_clt.restype = None
         L.orc_clt.argtypes = [vp, u64, u64, vp, vp]
+        L.orc_clt_blocks.restype = None
+        L.orc_clt_blocks.argtypes = [i32, i32, vp, u64, vp, vp]
         L.orc_clt_lookup.restype = u64
         L.orc_clt_lookup.argtypes = [vp, vp, u64]
         L.orc_neighbors.restype = None
         L.orc_neighbors.argtypes = [i32, i32, i32, vp, vp, vp, u64, u64, vp]
         L.orc_hv.restype = None
         L.orc_hv.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, u64, u64]
+        L.orc_full_table.restype = None
+        L.orc_full_table.argtypes = [i32, vp, u64, vp]
+        L.orc_hv_table.restype = None
+        L.orc_hv_table.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, u64, u64]
         L.orc_hv_rows.restype = None
         L.orc_hv_rows.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, u64]
         L.orc_stream_key.restype = u64
@@ -143,6 +149,15 @@ def clt(basis_arr, n_sites):
     return mask, prefix
 
 
+def clt_blocks(n_sites, n_up, blocks):
+    """(mask, prefix) of the listed blocks from the definition (no basis)."""
+    blocks = np.ascontiguousarray(blocks, dtype=np.uint64)
+    mask = np.empty(blocks.size, dtype=np.uint32)
+    prefix = np.empty(blocks.size, dtype=np.uint32)
+    lib().orc_clt_blocks(n_sites, n_up, _ptr(blocks), blocks.size, _ptr(mask), _ptr(prefix))
+    return mask, prefix
+
+
 def clt_lookup(mask, prefix, n):
     """Alg. 2 on the oracle's table."""
     return int(lib().orc_clt_lookup(_ptr(mask), _ptr(prefix), int(n)))
@@ -173,6 +188,24 @@ def hv(n_sites, n_up, bonds, x, basis_arr=None, row0=0, nrows=None):
     y = np.empty(nrows, dtype=np.float64)
     lib().orc_hv(n_sites, n_up, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), _ptr(basis_arr),
                  _ptr(x), _ptr(y), row0, nrows)
+    return y
+
+
+def full_table(n_sites, basis_arr):
+    """Full lookup table: uint32 index per label of [0, 2^N), 0xFFFFFFFF
+    outside the sector (Sec. 2, the simplest state-to-index map)."""
+    table = np.empty(1 << n_sites, dtype=np.uint32)
+    lib().orc_full_table(n_sites, _ptr(basis_arr), basis_arr.size, _ptr(table))
+    return table
+
+
+def hv_table(n_sites, n_up, bonds, x, basis_arr, table):
+    """FP64 H.x with partner indices from a full lookup table."""
+    bi, bj, J = _bonds(bonds)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(x.size, dtype=np.float64)
+    lib().orc_hv_table(n_sites, n_up, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), _ptr(basis_arr), _ptr(table),
+                       _ptr(x), _ptr(y), 0, x.size)
     return y
 
 

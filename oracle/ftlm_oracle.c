@@ -29,15 +29,23 @@ static int popcount64(uint64_t x) {
     return c;
 }
 
-/* Binomial coefficient C(n, k) as an exact integer, n <= 64. Zero outside
- * 0 <= k <= n. This is the spin-1/2 case of the dimension recursion D(m, A)
- * of Eq. (15): with digits in {0, 1}, D(m, A) = C(m, A). */
+/* Binomial coefficients C(n, k) for 0 <= k <= n <= 64 as exact integers,
+ * filled once at load time by Pascal's rule C(n, k) = C(n-1, k-1) + C(n-1, k)
+ * (every entry fits in 64 bits). This is the spin-1/2 case of the dimension
+ * recursion D(m, A) of Eq. (15): with digits in {0, 1}, D(m, A) = C(m, A). */
+static uint64_t pascal[65][65];
+
+__attribute__((constructor)) static void fill_pascal(void) {
+    for (int n = 0; n <= 64; ++n) {
+        pascal[n][0] = 1;
+        for (int k = 1; k <= n; ++k) pascal[n][k] = pascal[n - 1][k - 1] + (k < n ? pascal[n - 1][k] : 0);
+    }
+}
+
+/* C(n, k), zero outside 0 <= k <= n. */
 uint64_t orc_binom(int n, int k) {
-    if (n < 0 || k < 0 || k > n) return 0;
-    if (k > n - k) k = n - k;
-    unsigned __int128 c = 1;
-    for (int i = 1; i <= k; ++i) c = c * (unsigned)(n - k + i) / (unsigned)i;
-    return (uint64_t)c;
+    if (n < 0 || k < 0 || k > n || n > 64) return 0;
+    return pascal[n][k];
 }
 
 /* Sector dimension D_M = C(N, n_up). */
@@ -157,7 +165,7 @@ static uint64_t index_of(int n_sites, int n_up, const uint64_t* basis, uint64_t 
 void orc_neighbors(int n_sites, int n_up, int n_bonds, const int32_t* bi, const int32_t* bj,
                    const uint64_t* basis, uint64_t t0, uint64_t count, uint64_t* out) {
     uint64_t dim = orc_sector_dim(n_sites, n_up);
-#pragma omp parallel for schedule(dynamic, 256)
+#pragma omp parallel for schedule(dynamic, 256) if (count > 4096)
     for (int64_t r = 0; r < (int64_t)count; ++r) {
         uint64_t n = row_label(n_sites, n_up, basis, t0 + (uint64_t)r);
         for (int b = 0; b < n_bonds; ++b) {
@@ -182,7 +190,7 @@ void orc_hv(int n_sites, int n_up, int n_bonds, const int32_t* bi, const int32_t
             const double* J, const uint64_t* basis, const double* x, double* y, uint64_t row0,
             uint64_t nrows) {
     uint64_t dim = orc_sector_dim(n_sites, n_up);
-#pragma omp parallel for schedule(dynamic, 1024)
+#pragma omp parallel for schedule(dynamic, 1024) if (nrows > 4096)
     for (int64_t r = 0; r < (int64_t)nrows; ++r) {
         uint64_t t = row0 + (uint64_t)r;
         uint64_t n = row_label(n_sites, n_up, basis, t);
@@ -234,7 +242,7 @@ void orc_start_vector(uint64_t seed, int n_up, uint64_t r, int dist, uint64_t di
                       double* out) {
     uint64_t key = orc_stream_key(seed, n_up, r);
     const double two_pi = 2.0 * 3.141592653589793;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (dim > 65536)
     for (int64_t ii = 0; ii < (int64_t)dim; ++ii) {
         uint64_t i = (uint64_t)ii;
         double v;
@@ -257,13 +265,13 @@ void orc_start_vector(uint64_t seed, int n_up, uint64_t r, int dist, uint64_t di
 /* Batch forms of orc_rank / orc_unrank over arrays (OpenMP over entries). */
 void orc_rank_many(int n_sites, int n_up, const uint64_t* labels, uint64_t count,
                    uint64_t* out) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (count > 4096)
     for (int64_t i = 0; i < (int64_t)count; ++i) out[i] = orc_rank(n_sites, n_up, labels[i]);
 }
 
 void orc_unrank_many(int n_sites, int n_up, const uint64_t* idx, uint64_t count,
                      uint64_t* out) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (count > 1024)
     for (int64_t i = 0; i < (int64_t)count; ++i) out[i] = orc_unrank(n_sites, n_up, idx[i]);
 }
 
@@ -272,7 +280,7 @@ void orc_unrank_many(int n_sites, int n_up, const uint64_t* idx, uint64_t count,
 void orc_hv_rows(int n_sites, int n_up, int n_bonds, const int32_t* bi, const int32_t* bj,
                  const double* J, const uint64_t* basis, const double* x, double* y,
                  const uint64_t* rows, uint64_t nrows) {
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 64) if (nrows > 256)
     for (int64_t r = 0; r < (int64_t)nrows; ++r)
         orc_hv(n_sites, n_up, n_bonds, bi, bj, J, basis, x, y + r, rows[r], 1);
 }
@@ -280,3 +288,58 @@ void orc_hv_rows(int n_sites, int n_up, int n_bonds, const int32_t* bi, const in
 /* Output i (0-based) of a SplitMix64 generator seeded at s, for checking the
  * generator against its published output sequence. */
 uint64_t orc_splitmix64_output(uint64_t s, uint64_t i) { return mix64(s + (i + 1) * GAMMA); }
+
+/* Compressed-lookup-table entries of selected blocks straight from the
+ * definition (Eqs. 18-19): bit j of block b is set when label 32b + j (below
+ * 2^N) has n_up set bits; the prefix is the number of sector labels below
+ * 32b. Used where the full basis is too large to enumerate. */
+void orc_clt_blocks(int n_sites, int n_up, const uint64_t* blocks, uint64_t count, uint32_t* mask,
+                    uint32_t* prefix) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < (int64_t)count; ++i) {
+        uint64_t b = blocks[i];
+        uint32_t m = 0;
+        for (unsigned j = 0; j < 32; ++j) {
+            uint64_t label = b * 32 + j;
+            if ((n_sites >= 64 || (label >> n_sites) == 0) && popcount64(label) == n_up) m |= 1u << j;
+        }
+        mask[i] = m;
+        prefix[i] = (uint32_t)orc_count_below(n_sites, n_up, b * 32);
+    }
+}
+
+/* Full lookup table (Sec. 2, the simplest state-to-index map): one uint32
+ * per label of [0, 2^N), holding the sector index of sector labels and
+ * 0xFFFFFFFF elsewhere. Built from the sorted basis. 4 * 2^N bytes. */
+void orc_full_table(int n_sites, const uint64_t* basis, uint64_t dim, uint32_t* table) {
+    uint64_t size = (uint64_t)1 << n_sites;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < (int64_t)size; ++i) table[i] = 0xFFFFFFFFu;
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < (int64_t)dim; ++t) table[basis[t]] = (uint32_t)t;
+}
+
+/* H.x as orc_hv, with row labels from the stored basis and partner indices
+ * read from the full lookup table. */
+void orc_hv_table(int n_sites, int n_up, int n_bonds, const int32_t* bi, const int32_t* bj,
+                  const double* J, const uint64_t* basis, const uint32_t* table, const double* x,
+                  double* y, uint64_t row0, uint64_t nrows) {
+    (void)n_sites;
+    (void)n_up;
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t r = 0; r < (int64_t)nrows; ++r) {
+        uint64_t t = row0 + (uint64_t)r;
+        uint64_t n = basis[t];
+        double acc = 0.0;
+        for (int b = 0; b < n_bonds; ++b) {
+            int up_i = (int)((n >> bi[b]) & 1u), up_j = (int)((n >> bj[b]) & 1u);
+            double mi = up_i ? 0.5 : -0.5, mj = up_j ? 0.5 : -0.5;
+            acc += J[b] * mi * mj * x[t];
+            if (up_i != up_j) {
+                uint64_t partner = n ^ (((uint64_t)1 << bi[b]) | ((uint64_t)1 << bj[b]));
+                acc += 0.5 * J[b] * x[table[partner]];
+            }
+        }
+        y[r] = acc;
+    }
+}

@@ -1,0 +1,174 @@
+// Device-side building blocks shared by the libftlm kernels (gfx950, wave64).
+//
+// State labels (Sec. 2, Eq. 11 at s = 1/2): bit k of n is 1 when site k is
+// up. The sector with n_up up spins is ordered by increasing label, so the
+// index of a label is the number of sector labels below it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace ftlm {
+
+constexpr uint32_t kNone32 = 0xFFFFFFFFu;
+
+template <typename L>
+__device__ __forceinline__ int popc(L x) {
+    if constexpr (sizeof(L) == 8) return __popcll(x);
+    else return __popc(x);
+}
+
+// Binomial table staged in LDS: row p (0 <= p < N) has `w` entries and entry
+// [p][k + 1] is C(p, k) mod 2^32 for k in [-1, n_up + 1]. For s = 1/2 this is
+// the cumulative dimension table of Eq. (16): D_c(p, A, 1) = C(p, A).
+struct Binom {
+    const uint32_t* t;
+    int w;
+    __device__ __forceinline__ uint32_t operator()(int p, int k) const { return t[p * w + k + 1]; }
+};
+
+// Copies the sector's binomial table from HBM into LDS (all threads of the
+// block take part; ends with a barrier).
+__device__ __forceinline__ void stage_binomials(uint32_t* lds, const uint32_t* g, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) lds[i] = g[i];
+    __syncthreads();
+}
+
+// Unranking (the inverse map of Sec. 2, CR): walks the N digit positions
+// from the top in a loop of fixed length; at position p with A up spins still
+// to place, the C(p, A) labels with a 0 there come first, so the digit is 1
+// exactly when the remaining rank reaches C(p, A). Every C(p, A) compared lies
+// on the path of a valid rank and is <= D < 2^32, so the table's mod-2^32
+// entries are exact where they are compared.
+template <typename L>
+__device__ __forceinline__ L cr_unrank(uint32_t t, int n_sites, int n_up, Binom C) {
+    L n = 0;
+    uint32_t rem = t;
+    int A = n_up;
+    for (int p = n_sites - 1; p >= 0; --p) {
+        uint32_t c = C(p, A);
+        bool one = (A > 0) && (rem >= c);
+        if (one) {
+            n |= L(1) << p;
+            rem -= c;
+            A -= 1;
+        }
+    }
+    return n;
+}
+
+// Ranking, Alg. 1 at s = 1/2: over p = N-1..0, a 1 at position p adds
+// D_c(p, A, 1) = C(p, A) and lowers A. Sums wrap mod 2^32; the true rank is
+// < 2^32, so the wrapped sum is exact. The caller checks sector membership.
+template <typename L>
+__device__ __forceinline__ uint32_t cr_rank(L x, int n_sites, int n_up, Binom C) {
+    uint32_t r = 0;
+    int A = n_up;
+    for (int p = n_sites - 1; p >= 0; --p) {
+        uint32_t bit = uint32_t((x >> p) & 1);
+        r += bit ? C(p, A) : 0u;
+        A -= int(bit);
+    }
+    return r;
+}
+
+// Alg. 2: index of label n through the compressed lookup table, kNone32 when
+// bit n mod 32 of the block's mask is clear.
+__device__ __forceinline__ uint32_t clt_lookup(const CltEntry* clt, uint32_t n) {
+    CltEntry e = clt[n >> 5];
+    uint32_t j = n & 31u;
+    if (((e.mask >> j) & 1u) == 0) return kNone32;
+    return e.prefix + __popc(e.mask & ((1u << j) - 1u));
+}
+
+// Bonds as the kernels see them (passed by value as a kernel argument, so
+// every read is a wave-uniform scalar load): sorted by their lower site,
+// highest first, so the combinatorial-ranking pass, which walks the sites
+// from the top, meets each bond at its lower site after its upper site is
+// known. The bonds with lower site >= p are the first ends[p] entries.
+struct BondTable {
+    uint8_t lo[kMaxBonds];
+    uint8_t hi[kMaxBonds];
+    uint8_t orig[kMaxBonds];   // position of the bond in the caller's order
+    float coef_f[kMaxBonds];   // J_b / 2 (Eqs. 13-14 at s = 1/2)
+    double coef_d[kMaxBonds];
+    uint16_t ends[kMaxSites + 1];
+    int n_bonds;
+    int n_sites;
+    float jsum4_f;   // sum_b J_b / 4: the diagonal when every bond is parallel
+    double jsum4_d;
+};
+
+// Visits one row t of the sector: finds its label n_t and, for every bond,
+// either reports a parallel pair or the sector index of the flipped partner
+// n_t ^ (2^i + 2^j) (Eq. 12 at s = 1/2). The visitor receives
+//   v.flip(b, idx)  for an antiparallel bond b (b in the sorted order), and
+//   v.par(b)        for a parallel one.
+//
+// CLT mode reads n_t from the stored basis and looks partners up with Alg. 2
+// (the occupancy test always passes for a flip inside the sector, Sec. 2).
+//
+// CR mode reconstructs n_t by unranking and, in the same top-down pass over
+// the sites, ranks every partner in O(1): with K = number of up spins at
+// positions <= p, Es/Fs the sums over up positions q above p of
+// C(q, K_q - 1) - C(q, K_q) and C(q, K_q + 1) - C(q, K_q), define
+//   up p:   X = Es - C(p, K),     Y = -C(p, K + 1) - Fs
+//   down p: X = C(p, K + 1) + Fs, Y = C(p, K) - Es.
+// Moving the up spin of an antiparallel pair lo < hi to the other site changes
+// Alg. 1's sum by X(lo) + Y(hi) in both directions (every term between lo and
+// hi whose K shifts by one telescopes into Es/Fs), so the partner's index is
+// t + X(lo) + Y(hi) mod 2^32. Y of the sites above p sits in LDS at
+// ylds[q * 64] (this lane's column of its wave's slab, bank-conflict free).
+template <typename L, int MODE, typename V>
+__device__ __forceinline__ L visit_row(uint32_t t, int n_up, const BondTable& B, Binom C,
+                                       const uint32_t* __restrict__ basis,
+                                       const CltEntry* __restrict__ clt, uint32_t* ylds, V& v) {
+    if constexpr (MODE == kModeClt) {
+        const uint32_t n = basis[t];
+        for (int b = 0; b < B.n_bonds; ++b) {
+            const uint32_t si = (n >> B.lo[b]) & 1u, sj = (n >> B.hi[b]) & 1u;
+            if (si != sj) {
+                const uint32_t m = n ^ ((1u << B.lo[b]) | (1u << B.hi[b]));
+                const CltEntry e = clt[m >> 5];
+                v.flip(b, e.prefix + __popc(e.mask & ((1u << (m & 31u)) - 1u)));
+            } else {
+                v.par(b);
+            }
+        }
+        return L(n);
+    } else {
+        L n = 0;
+        uint32_t rem = t, Es = 0, Fs = 0;
+        int A = n_up;
+        int b = 0;
+        for (int p = B.n_sites - 1; p >= 0; --p) {
+            const uint32_t cm = C(p, A - 1), c0 = C(p, A), cp = C(p, A + 1);
+            const bool one = (A > 0) && (rem >= c0);
+            uint32_t X, Y;
+            if (one) {
+                X = Es - c0;
+                Y = 0u - cp - Fs;
+                Es += cm - c0;
+                Fs += cp - c0;
+                rem -= c0;
+                A -= 1;
+                n |= L(1) << p;
+            } else {
+                X = cp + Fs;
+                Y = c0 - Es;
+            }
+            ylds[p * 64] = Y;
+            const int end = B.ends[p];
+            for (; b < end; ++b) {
+                const uint32_t shi = uint32_t((n >> B.hi[b]) & 1);
+                if (shi != uint32_t(one)) v.flip(b, t + X + ylds[B.hi[b] * 64]);
+                else v.par(b);
+            }
+        }
+        return n;
+    }
+}
+
+}  // namespace ftlm

@@ -1,0 +1,122 @@
+// Host FP64 parts of the FTLM path: the Ritz decomposition of the Lanczos
+// tridiagonal matrix and the thermal reduction (paper Sec. 2: the small
+// tridiagonal problem is solved on the host in FP64; Eqs. 4-9).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "host_math.hpp"
+
+namespace ftlm {
+
+// Implicit-shift QL iteration on the symmetric tridiagonal matrix with
+// diagonal d[0..m-1] and off-diagonal e[i] coupling rows i and i+1. Each
+// sweep applies Givens rotations from the bottom of the unreduced block
+// [l, k] upwards (QL factorization of T - sigma I with the shift sigma taken
+// from the eigenvalue of the leading 2x2 block nearer to d[l]), so the
+// eigenvalue d[l] converges first. The rotations are also applied to the
+// first row of the accumulated eigenvector matrix, which is all FTLM needs:
+// w_k = (first component of eigenvector k)^2.
+int ritz_ql(int m, const double* alpha, const double* beta, double* theta, double* weight) {
+    std::vector<double> d(alpha, alpha + m), e(size_t(m), 0.0), z(size_t(m), 0.0);
+    for (int i = 0; i + 1 < m; ++i) e[size_t(i)] = beta[i];
+    z[0] = 1.0;
+    const double eps = 2.220446049250313e-16;
+    for (int l = 0; l < m; ++l) {
+        for (int iter = 0;; ++iter) {
+            int k = l;
+            while (k < m - 1 && std::fabs(e[size_t(k)]) > eps * (std::fabs(d[size_t(k)]) + std::fabs(d[size_t(k + 1)])))
+                ++k;
+            if (k == l) break;
+            if (iter >= 200) return -1;
+            // shift toward d[l] from the leading 2x2 block
+            double g = (d[size_t(l + 1)] - d[size_t(l)]) / (2.0 * e[size_t(l)]);
+            double r = std::hypot(g, 1.0);
+            g = d[size_t(k)] - d[size_t(l)] + e[size_t(l)] / (g + std::copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool deflated = false;
+            for (int i = k - 1; i >= l; --i) {
+                const double f = s * e[size_t(i)], b = c * e[size_t(i)];
+                r = std::hypot(f, g);
+                e[size_t(i + 1)] = r;
+                if (r == 0.0) {  // the block split: finish this sweep early
+                    d[size_t(i + 1)] -= p;
+                    e[size_t(k)] = 0.0;
+                    deflated = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[size_t(i + 1)] - p;
+                r = (d[size_t(i)] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[size_t(i + 1)] = g + p;
+                g = c * r - b;
+                const double zi = z[size_t(i)], zn = z[size_t(i + 1)];
+                z[size_t(i + 1)] = s * zi + c * zn;
+                z[size_t(i)] = c * zi - s * zn;
+            }
+            if (deflated) continue;
+            d[size_t(l)] -= p;
+            e[size_t(l)] = g;
+            e[size_t(k)] = 0.0;
+        }
+    }
+    std::vector<int> order(static_cast<size_t>(m));
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d[size_t(a)] < d[size_t(b)]; });
+    for (int i = 0; i < m; ++i) {
+        theta[i] = d[size_t(order[size_t(i)])];
+        const double zi = z[size_t(order[size_t(i)])];
+        weight[i] = zi * zi;
+    }
+    return 0;
+}
+
+// FTLM thermal reduction (Eqs. 6-9). Per sector the estimator weighs each
+// sample's Gauss-quadrature sum by mult * D / R; Boltzmann factors use
+// theta - E0 with E0 the smallest Ritz value of all samples, which cancels in
+// every ratio and keeps the exponentials in range.
+int thermo(int n_sites, int n_sectors, const SectorSamples* sec, int nT, const double* T,
+           double g, double* E, double* C, double* chi, double* lnZ) {
+    double e0 = INFINITY;
+    for (int s = 0; s < n_sectors; ++s)
+        for (int r = 0; r < sec[s].R; ++r)
+            for (int k = 0; k < sec[s].steps[r]; ++k)
+                e0 = std::min(e0, sec[s].theta[size_t(r) * size_t(sec[s].stride) + size_t(k)]);
+    if (!std::isfinite(e0)) return -1;
+    for (int it = 0; it < nT; ++it) {
+        const double beta = 1.0 / T[it];
+        double z = 0.0, h1 = 0.0, h2 = 0.0, zm2 = 0.0;
+        for (int s = 0; s < n_sectors; ++s) {
+            const SectorSamples& q = sec[s];
+            const double pref = q.mult * double(q.dim) / double(q.R);
+            const double mz = double(q.n_up) - 0.5 * double(n_sites);
+            double zs = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int r = 0; r < q.R; ++r) {
+                const double* th = q.theta + size_t(r) * size_t(q.stride);
+                const double* w = q.weight + size_t(r) * size_t(q.stride);
+                for (int k = 0; k < q.steps[r]; ++k) {
+                    const double x = th[k] - e0;
+                    const double bw = w[k] * std::exp(-beta * x);
+                    zs += bw;
+                    a1 += bw * x;
+                    a2 += bw * x * x;
+                }
+            }
+            z += pref * zs;
+            h1 += pref * a1;
+            h2 += pref * a2;
+            zm2 += mz * mz * pref * zs;
+        }
+        const double mean = h1 / z;
+        if (E) E[it] = e0 + mean;
+        if (C) C[it] = beta * beta * (h2 / z - mean * mean);
+        if (chi) chi[it] = g * g * beta * zm2 / z;
+        if (lnZ) lnZ[it] = std::log(z) - beta * e0;
+    }
+    return 0;
+}
+
+}  // namespace ftlm

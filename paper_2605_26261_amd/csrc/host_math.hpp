@@ -1,0 +1,24 @@
+// Host FP64 helpers: Ritz decomposition and thermal reduction.
+#pragma once
+
+#include <stdint.h>
+
+namespace ftlm {
+
+struct SectorSamples {
+    int n_up;
+    int R;
+    int stride;
+    uint64_t dim;
+    double mult;
+    const double* theta;
+    const double* weight;
+    const int32_t* steps;
+};
+
+int ritz_ql(int m, const double* alpha, const double* beta, double* theta, double* weight);
+
+int thermo(int n_sites, int n_sectors, const SectorSamples* sec, int nT, const double* T,
+           double g, double* E, double* C, double* chi, double* lnZ);
+
+}  // namespace ftlm

@@ -1,0 +1,7 @@
+// FP32 instantiations of the H.x kernels.
+#include "hv_impl.hpp"
+
+namespace ftlm {
+template hipError_t launch_hv_typed<float>(const SectorDev&, const BondTable&, const HvLaunch&,
+                                           hipStream_t);
+}  // namespace ftlm

@@ -1,0 +1,85 @@
+// Row-tile scheduling and deterministic FP64 block reductions shared by the
+// persistent row kernels.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace ftlm {
+
+// Calls f(tile) for the tiles of kBlock rows this workgroup owns. With a grid
+// that is a multiple of 8, workgroup i runs on XCD i mod 8 (round-robin
+// dispatch), so XCD x gets the x-th contiguous eighth of the tiles and its
+// L2 sees neighbouring rows; inside a share the XCD's workgroups stride.
+template <typename F>
+__device__ __forceinline__ void for_each_tile(uint32_t ntiles, F&& f) {
+    const uint32_t G = gridDim.x;
+    if (G >= 8 && (G & 7u) == 0) {
+        const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3, per = G >> 3;
+        const uint32_t chunk = (ntiles + 7u) >> 3;
+        const uint32_t begin = xcd * chunk;
+        const uint32_t end = begin + chunk < ntiles ? begin + chunk : ntiles;
+        for (uint32_t tile = begin + slot; tile < end; tile += per) f(tile);
+    } else {
+        for (uint32_t tile = blockIdx.x; tile < ntiles; tile += G) f(tile);
+    }
+}
+
+// Sums v[0..N) over the workgroup in a fixed order (butterfly inside each
+// wave, then the waves in order). red must hold (kWaves + 1) * N doubles;
+// after the call red[kWaves * N + c] holds the block total of column c,
+// visible to all threads.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        double x = v[c];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[wave * N + c] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double s = 0.0;
+        for (int w = 0; w < kWaves; ++w) s += red[w * N + threadIdx.x];
+        red[kWaves * N + threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Publishes this block's partials and reports whether it is the last block
+// of the grid to do so (then every partial is visible to it). The ticket is
+// reset by that last block for the next launch on the stream.
+__device__ __forceinline__ bool last_block(uint32_t* ticket, int* flag_lds) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(ticket, 1u);
+        *flag_lds = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *flag_lds != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Fixed-order sum over the G block partials of one column,
+// partials[g * pstride + col]: thread i sums blocks i, i + kBlock, ..., then
+// the block combines the threads as a tree, so the order depends on G only.
+// Returns the total in every thread. red holds kBlock doubles.
+__device__ __forceinline__ double grid_sum_col(const double* partials, int G, int pstride, int col,
+                                               double* red) {
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) s += partials[size_t(g) * pstride + col];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int half = kBlock / 2; half >= 1; half >>= 1) {
+        if (threadIdx.x < half) red[threadIdx.x] += red[threadIdx.x + half];
+        __syncthreads();
+    }
+    const double total = red[0];
+    __syncthreads();
+    return total;
+}
+
+}  // namespace ftlm

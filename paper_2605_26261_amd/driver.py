@@ -1,0 +1,52 @@
+"""FTLM runs through libftlm: per sector, R Lanczos chains on the device,
+Ritz values on the host, then the thermal reduction (paper Sec. 2, Eqs. 4-9).
+
+Orchestration only; every numerical step is a library call.
+"""
+import numpy as np
+
+from . import ftlm
+
+
+def multiplicity(n_sites, n_up):
+    """Sectors +M and -M share a spectrum (Sec. 2): weight 2 for M > 0."""
+    return 1.0 if 2 * n_up == n_sites else 2.0
+
+
+def log_temperatures(n=200, t_min=0.05, t_max=10.0):
+    k = np.arange(n)
+    return t_min * (t_max / t_min) ** (k / (n - 1))
+
+
+def sector_samples(sector, graph, R, M, seed, dist, dtype, r0=0, work=None, stream=None):
+    """Runs R chains in one batch; returns the thermo record of the sector."""
+    alpha, beta, steps = ftlm.lanczos(sector, graph, seed, r0, R, M, dist, dtype, work=work, stream=stream)
+    theta = np.zeros((R, M))
+    weight = np.zeros((R, M))
+    for r in range(R):
+        k = int(steps[r])
+        th, w = ftlm.ritz(alpha[r, :k], beta[r, :max(k - 1, 1)], k)
+        theta[r, :k] = th
+        weight[r, :k] = w
+    return {"n_up": sector.n_up, "dim": sector.dim, "mult": multiplicity(sector.n_sites, sector.n_up),
+            "theta": theta, "weight": weight, "steps": steps, "alpha": alpha, "beta": beta}
+
+
+def run(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, temps=None, g=1.0,
+        batch=None, device="cuda"):
+    """Full FTLM over the listed sectors. Chains run in batches of `batch`
+    (default: all R at once). Returns (thermo dict, per-sector records)."""
+    temps = log_temperatures() if temps is None else temps
+    graph = ftlm.Graph(n_sites, bonds)
+    recs = []
+    for n_up in n_ups:
+        sec = ftlm.Sector(n_sites, n_up, mode, device=device)
+        b = R if batch is None else batch
+        parts = []
+        for r0 in range(0, R, b):
+            parts.append(sector_samples(sec, graph, min(b, R - r0), M, seed, dist, dtype, r0=r0))
+        rec = {k: parts[0][k] for k in ("n_up", "dim", "mult")}
+        for k in ("theta", "weight", "steps", "alpha", "beta"):
+            rec[k] = np.concatenate([p[k] for p in parts])
+        recs.append(rec)
+    return ftlm.thermo(n_sites, recs, temps, g), recs

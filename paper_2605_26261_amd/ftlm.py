@@ -1,0 +1,276 @@
+"""Thin Python binding of libftlm (include/ftlm.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels or its host C++. Device buffers are torch tensors on a HIP device;
+streams default to torch's current stream. Names mirror the C entry points
+without the ``ftlm_`` prefix (``hv`` is ``ftlm_hv``).
+
+Importing this module raises ImportError when libftlm.so is missing; there
+is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libftlm.so")
+
+OK, E_INVALID, E_RANGE, E_NOSPACE, E_DEVICE, E_AGAIN, E_REJECTED = 0, -1, -2, -3, -4, -5, -6
+CLT, CR = 0, 1
+F32, F64 = 0, 1
+PM1, GAUSS, UNIT = 0, 1, 2
+NONE = (1 << 64) - 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libftlm.so not found at {LIB_PATH}: build it with paper_2605_26261_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp, _u64, _i32, _i64, _sz, _dbl = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64,
+                                    ctypes.c_size_t, ctypes.c_double)
+
+
+class SectorResult(ctypes.Structure):
+    """ftlm_sector_result."""
+    _fields_ = [("n_up", ctypes.c_int32), ("R", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("dim", ctypes.c_uint64), ("mult", ctypes.c_double),
+                ("theta", _vp), ("weight", _vp), ("steps", _vp)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("ftlm_last_error", ctypes.c_char_p, [])
+_sig("ftlm_version", _i32, [])
+_sig("ftlm_graph_create", _i32, [_i32, _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)])
+_sig("ftlm_graph_destroy", None, [_vp])
+_sig("ftlm_graph_n_sites", _i32, [_vp])
+_sig("ftlm_graph_n_bonds", _i32, [_vp])
+_sig("ftlm_sector_table_bytes", _i32, [_i32, _i32, _i32, ctypes.POINTER(_sz)])
+_sig("ftlm_sector_create", _i32, [_i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)])
+_sig("ftlm_sector_dim", _u64, [_vp])
+_sig("ftlm_sector_mode", _i32, [_vp])
+_sig("ftlm_sector_destroy", None, [_vp])
+_sig("ftlm_rank", _i32, [_vp, _vp, _vp, _u64, _vp])
+_sig("ftlm_unrank", _i32, [_vp, _vp, _vp, _u64, _vp])
+_sig("ftlm_clt_export", _i32, [_vp, _vp, _vp, _u64, _vp])
+_sig("ftlm_neighbors", _i32, [_vp, _vp, _u64, _u64, _vp, _vp])
+_sig("ftlm_hv", _i32, [_vp, _vp, _vp, _vp, _i32, _i32, _vp])
+_sig("ftlm_hv_rows", _i32, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _u64, _vp])
+_sig("ftlm_start_vectors", _i32, [_vp, _u64, _u64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
+_sig("ftlm_lanczos_workspace_bytes", _i32, [_vp, _i32, _i32, ctypes.POINTER(_sz)])
+_sig("ftlm_lanczos", _i32, [_vp, _vp, _u64, _u64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _vp])
+_sig("ftlm_ritz", _i32, [_i32, _vp, _vp, _vp, _vp])
+_sig("ftlm_thermo", _i32, [_i32, _i32, ctypes.POINTER(SectorResult), _i32, _vp, _dbl, _vp, _vp, _vp, _vp])
+_sig("ftlm_stats_enable", _i32, [_i32])
+_sig("ftlm_stats_reset", _i32, [])
+_sig("ftlm_stats_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)])
+
+
+class FtlmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libftlm error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise FtlmError(rc, _lib.ftlm_last_error().decode())
+    return rc
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (contiguous, on a HIP device)."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _empty_device(nbytes, device="cuda"):
+    import torch
+    return torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device=device)
+
+
+def version():
+    return _lib.ftlm_version()
+
+
+class Graph:
+    """ftlm_graph: bonds [(i, j, J)] on n_sites sites."""
+
+    def __init__(self, n_sites, bonds):
+        bi = np.ascontiguousarray([b[0] for b in bonds], dtype=np.int32)
+        bj = np.ascontiguousarray([b[1] for b in bonds], dtype=np.int32)
+        J = np.ascontiguousarray([b[2] for b in bonds], dtype=np.float64)
+        h = _vp()
+        _check(_lib.ftlm_graph_create(n_sites, len(bonds), _hptr(bi), _hptr(bj), _hptr(J), ctypes.byref(h)))
+        self.handle = h
+        self.n_sites = n_sites
+
+    @property
+    def n_bonds(self):
+        return _lib.ftlm_graph_n_bonds(self.handle)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.ftlm_graph_destroy(self.handle)
+            self.handle = None
+
+
+def sector_table_bytes(n_sites, n_up, mode):
+    n = _sz()
+    _check(_lib.ftlm_sector_table_bytes(n_sites, n_up, mode, ctypes.byref(n)))
+    return n.value
+
+
+class Sector:
+    """ftlm_sector with its device table buffer (owned by this object)."""
+
+    def __init__(self, n_sites, n_up, mode, device="cuda", stream=None, table=None):
+        nbytes = sector_table_bytes(n_sites, n_up, mode)
+        self.table = table if table is not None else _empty_device(nbytes, device)
+        h = _vp()
+        _check(_lib.ftlm_sector_create(n_sites, n_up, mode, _dptr(self.table), self.table.numel(),
+                                       _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.n_sites, self.n_up, self.mode = n_sites, n_up, mode
+
+    @property
+    def dim(self):
+        return int(_lib.ftlm_sector_dim(self.handle))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.ftlm_sector_destroy(self.handle)
+            self.handle = None
+
+
+def rank(sector, labels, idx, stream=None):
+    _check(_lib.ftlm_rank(sector.handle, _dptr(labels), _dptr(idx), labels.numel(), _stream(stream)))
+
+
+def unrank(sector, idx, labels, stream=None):
+    _check(_lib.ftlm_unrank(sector.handle, _dptr(idx), _dptr(labels), idx.numel(), _stream(stream)))
+
+
+def clt_export(sector, nblocks, stream=None):
+    mask = np.empty(nblocks, dtype=np.uint32)
+    prefix = np.empty(nblocks, dtype=np.uint32)
+    _check(_lib.ftlm_clt_export(sector.handle, _hptr(mask), _hptr(prefix), nblocks, _stream(stream)))
+    return mask, prefix
+
+
+def neighbors(sector, graph, t0, count, out, stream=None):
+    _check(_lib.ftlm_neighbors(sector.handle, graph.handle, t0, count, _dptr(out), _stream(stream)))
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise ValueError("vectors must be float32 or float64")
+
+
+def hv(sector, graph, x, y, stream=None):
+    """y = H x for x, y of shape [D] or [D, B]."""
+    nvec = 1 if x.dim() == 1 else x.shape[1]
+    _check(_lib.ftlm_hv(sector.handle, graph.handle, _dptr(x), _dptr(y), nvec, _dtype_code(x), _stream(stream)))
+
+
+def hv_rows(sector, graph, x, y, row0, nrows, stream=None):
+    nvec = 1 if x.dim() == 1 else x.shape[1]
+    _check(_lib.ftlm_hv_rows(sector.handle, graph.handle, _dptr(x), _dptr(y), nvec, _dtype_code(x),
+                             row0, nrows, _stream(stream)))
+
+
+def lanczos_workspace_bytes(sector, R, dtype):
+    n = _sz()
+    _check(_lib.ftlm_lanczos_workspace_bytes(sector.handle, R, dtype, ctypes.byref(n)))
+    return n.value
+
+
+def start_vectors(sector, seed, r0, R, dist, q, work, stream=None):
+    """Writes R start vectors into q [D, R]; returns their FP64 norms."""
+    norms = np.empty(R, dtype=np.float64)
+    _check(_lib.ftlm_start_vectors(sector.handle, seed, r0, R, dist, _dtype_code(q), _dptr(q), _hptr(norms),
+                                   _dptr(work), work.numel(), _stream(stream)))
+    return norms
+
+
+def lanczos(sector, graph, seed, r0, R, M, dist, dtype, work=None, stream=None):
+    """R Lanczos chains; returns (alpha [R, M], beta [R, M], steps [R])."""
+    if work is None:
+        work = _empty_device(lanczos_workspace_bytes(sector, R, dtype), sector.table.device)
+    alpha = np.zeros((R, M), dtype=np.float64)
+    beta = np.zeros((R, M), dtype=np.float64)
+    steps = np.zeros(R, dtype=np.int32)
+    _check(_lib.ftlm_lanczos(sector.handle, graph.handle, seed, r0, R, M, dist, dtype, _dptr(work), work.numel(),
+                             _hptr(alpha), _hptr(beta), _hptr(steps), _stream(stream)))
+    return alpha, beta, steps
+
+
+def ritz(alpha, beta, m=None):
+    """Ritz values and weights of the m x m tridiagonal matrix (host FP64)."""
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    m = len(alpha) if m is None else m
+    theta = np.empty(m, dtype=np.float64)
+    weight = np.empty(m, dtype=np.float64)
+    _check(_lib.ftlm_ritz(m, _hptr(alpha), _hptr(beta), _hptr(theta), _hptr(weight)))
+    return theta, weight
+
+
+def thermo(n_sites, sectors, temps, g=1.0):
+    """sectors: list of dicts n_up, dim, mult, theta [R, S], weight [R, S], steps [R]."""
+    keep = []
+    recs = (SectorResult * len(sectors))()
+    for i, s in enumerate(sectors):
+        th = np.ascontiguousarray(s["theta"], dtype=np.float64)
+        w = np.ascontiguousarray(s["weight"], dtype=np.float64)
+        st = np.ascontiguousarray(s["steps"], dtype=np.int32)
+        keep += [th, w, st]
+        recs[i] = SectorResult(s["n_up"], th.shape[0], th.shape[1], 0, s["dim"], s["mult"],
+                               th.ctypes.data, w.ctypes.data, st.ctypes.data)
+    temps = np.ascontiguousarray(temps, dtype=np.float64)
+    out = {k: np.empty(len(temps)) for k in ("E", "C", "chi", "lnZ")}
+    _check(_lib.ftlm_thermo(n_sites, len(sectors), recs, len(temps), _hptr(temps), g, _hptr(out["E"]),
+                            _hptr(out["C"]), _hptr(out["chi"]), _hptr(out["lnZ"])))
+    return out
+
+
+def stats_enable(on=True):
+    _check(_lib.ftlm_stats_enable(1 if on else 0))
+
+
+def stats_reset():
+    _check(_lib.ftlm_stats_reset())
+
+
+def stats_read():
+    n = _i64()
+    ms = ctypes.c_double()
+    _check(_lib.ftlm_stats_read(ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def exported_symbols():
+    """Names of the C entry points this binding loads."""
+    return [n for n in dir(_lib) if n.startswith("ftlm_")]

@@ -1,0 +1,136 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/ftlm.h declares, validates arguments, and its host FP64 parts (Ritz
+values, thermal reduction) agree with the oracle. No GPU call is made."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from ftlm_inputs import graphs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ftlm():
+    from paper_2605_26261_amd import ftlm as m
+    return m
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ftlm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ftlm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function(ftlm):
+    names = declared_functions()
+    assert len(names) >= 25
+    lib = ctypes.CDLL(ftlm.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_sizes(ftlm):
+    assert ftlm.version() == 1
+    # CLT mode at N = 30: basis (4 D bytes) + table (8 bytes per 32 labels)
+    d = math.comb(30, 15)
+    clt = ftlm.sector_table_bytes(30, 15, ftlm.CLT)
+    assert 4 * d + 8 * 2 ** 25 <= clt <= 4 * d + 8 * 2 ** 25 + 4096
+    # CR mode: binomials only (a few KB)
+    assert ftlm.sector_table_bytes(30, 15, ftlm.CR) < 4096
+    assert ftlm.sector_table_bytes(34, 17, ftlm.CR) < 4096
+
+
+@pytest.mark.parametrize("args,code", [
+    ((30, 15, 7), -1),      # bad mode
+    ((33, 16, 0), -2),      # CLT past 32 sites
+    ((40, 20, 1), -2),      # D >= 2^32
+    ((65, 3, 1), -2),       # N > 64
+    ((10, 11, 1), -1),      # n_up > N
+])
+def test_sector_bytes_errors(ftlm, args, code):
+    with pytest.raises(ftlm.FtlmError) as e:
+        ftlm.sector_table_bytes(*args)
+    assert e.value.code == code
+
+
+def test_graph_validation(ftlm):
+    g = ftlm.Graph(6, [(0, 1, 1.0), (1, 0, 0.5), (2, 3, 1.0)])
+    assert g.n_bonds == 2  # (0,1) and (1,0) merge
+    for bad in ([(0, 6, 1.0)], [(2, 2, 1.0)], [(-1, 2, 1.0)], [(0, 1, float("nan"))]):
+        with pytest.raises(ftlm.FtlmError) as e:
+            ftlm.Graph(6, bad)
+        assert e.value.code == ftlm.E_INVALID
+    with pytest.raises(ftlm.FtlmError):
+        ftlm.Graph(65, [(0, 1, 1.0)])
+    with pytest.raises(ftlm.FtlmError):
+        ftlm.Graph(30, [(i, j, 1.0) for i in range(30) for j in range(i + 1, 30)][:129])
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 40, 100, 300])
+def test_ritz_matches_oracle(ftlm, m):
+    rng = np.random.default_rng(m)
+    a = rng.standard_normal(m) * 3
+    b = np.abs(rng.standard_normal(max(m - 1, 1))) + 0.05
+    if m > 10:
+        b[m // 3] = 1e-300  # a split block
+    th, w = ftlm.ritz(a, b, m)
+    th_o, w_o = oracle.ritz(a, b, m)
+    np.testing.assert_allclose(th, th_o, rtol=0, atol=1e-12 * max(1, np.abs(th_o).max()))
+    assert abs(w.sum() - 1.0) < 1e-13
+    # weights may split differently inside exactly degenerate clusters only
+    np.testing.assert_allclose(w, w_o, atol=1e-10)
+
+
+def test_ritz_on_a_lanczos_matrix_with_ghosts(ftlm):
+    # a long FP64 run without reorthogonalization produces near-degenerate
+    # Ritz values; the quadrature moments must still agree with the oracle
+    n, n_up = 12, 6
+    bonds = graphs.ring(12)
+    b = oracle.basis(n, n_up)
+    q = oracle.start_vector(5, n_up, 0, oracle.GAUSS, len(b))
+    a, bb, k = oracle.lanczos(lambda v: oracle.hv(n, n_up, bonds, v, b), q, 200)
+    th, w = ftlm.ritz(a, bb, k)
+    th_o, w_o = oracle.ritz(a, bb, k)
+    for p in range(5):
+        assert abs((w * th ** p).sum() - (w_o * th_o ** p).sum()) < 1e-9 * max(1, abs((w_o * th_o ** p).sum()))
+
+
+def test_thermo_matches_oracle(ftlm):
+    n = 10
+    bonds = graphs.random_cluster(n, np.random.default_rng(3))
+    temps = oracle.log_temperatures()
+    recs_o, recs_l = [], []
+    for n_up in range(5, 11):
+        rec, raw = oracle.ftlm_sector(n, n_up, bonds, 4, 30, 9, oracle.PM1)
+        recs_o.append(rec)
+        S = max(k for *_, k in raw)
+        th = np.zeros((4, S))
+        w = np.zeros((4, S))
+        steps = np.zeros(4, dtype=np.int32)
+        for r, (t_, w_) in enumerate(rec["samples"]):
+            th[r, :len(t_)] = t_
+            w[r, :len(w_)] = w_
+            steps[r] = len(t_)
+        recs_l.append({"n_up": n_up, "dim": rec["dim"], "mult": float(rec["mult"]), "theta": th, "weight": w,
+                       "steps": steps})
+    for g in (1.0, 2.0):
+        want = oracle.thermo(recs_o, temps, n, g)
+        got = ftlm.thermo(n, recs_l, temps, g)
+        for key in ("E", "C", "chi", "lnZ"):
+            np.testing.assert_allclose(got[key], want[key], rtol=1e-11, atol=1e-13)
+
+
+def test_thermo_rejects_bad_input(ftlm):
+    rec = {"n_up": 1, "dim": 2, "mult": 1.0, "theta": np.zeros((1, 2)), "weight": np.ones((1, 2)),
+           "steps": np.array([3], dtype=np.int32)}
+    with pytest.raises(ftlm.FtlmError):
+        ftlm.thermo(2, [rec], [1.0])
+    rec["steps"] = np.array([2], dtype=np.int32)
+    with pytest.raises(ftlm.FtlmError):
+        ftlm.thermo(2, [rec], [0.0])

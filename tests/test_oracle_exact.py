@@ -118,10 +118,11 @@ def test_clt_lookup_equals_rank(n):
         b = oracle.basis(n, n_up)
         mask, prefix = oracle.clt(b, n)
         assert mask.size == max(1, (2 ** n + 31) // 32)
-        for x in range(2 ** n) if n <= 10 else np.random.default_rng(n).integers(0, 2 ** n, 3000):
-            want = oracle.rank(n, n_up, np.array([x], dtype=np.uint64))[0]
-            got = oracle.clt_lookup(mask, prefix, int(x))
-            assert (got == int(NONE)) if want == NONE else (got == int(want))
+        xs = np.arange(2 ** n, dtype=np.uint64) if n <= 10 else \
+            np.random.default_rng(n).integers(0, 2 ** n, 3000).astype(np.uint64)
+        want = oracle.rank(n, n_up, xs)
+        got = np.array([oracle.clt_lookup(mask, prefix, int(x)) for x in xs], dtype=np.uint64)
+        np.testing.assert_array_equal(got, want)
 
 
 def test_clt_block_masks_closed_form():
@@ -306,3 +307,22 @@ def test_ed_pin_itself_closed_forms():
                           (4, graphs.ring(4), [-2.0] + [-1.0] * 3 + [0.0] * 7 + [1.0] * 5)]:
         ev = np.linalg.eigvalsh(ed.hamiltonian(n, bonds).toarray())
         np.testing.assert_allclose(np.sort(ev), np.sort(exp), atol=1e-12)
+
+
+def test_full_table_and_block_definitions_agree():
+    # the full lookup table and the per-block CLT definition (used where the
+    # basis is too large to scan) against the basis-based forms
+    n, n_up = 18, 8
+    bonds = graphs.random_cluster(n, np.random.default_rng(6))
+    b = oracle.basis(n, n_up)
+    table = oracle.full_table(n, b)
+    labels = np.arange(2 ** n, dtype=np.uint64)
+    r = oracle.rank(n, n_up, labels)
+    np.testing.assert_array_equal(table.astype(np.uint64), np.where(r == NONE, np.uint64(0xFFFFFFFF), r))
+    x = np.random.default_rng(1).standard_normal(len(b))
+    np.testing.assert_array_equal(oracle.hv_table(n, n_up, bonds, x, b, table), oracle.hv(n, n_up, bonds, x, b))
+    mask, prefix = oracle.clt(b, n)
+    blocks = np.arange(mask.size)
+    m2, p2 = oracle.clt_blocks(n, n_up, blocks)
+    np.testing.assert_array_equal(mask, m2)
+    np.testing.assert_array_equal(prefix, p2)
