@@ -152,13 +152,48 @@ def cpu_baseline(target_s=15.0):
                       f"(count-based ranks, no stored basis), {dt:.1f} s"}
 
 
+def profile_kernels():
+    """Short run for hardware-counter passes: per index map, one 3-step
+    Lanczos run over the 20-chain block (3 Lanczos-epilogue H.x launches and 3
+    updates) and 3 single-vector H.x launches; then a plain device copy of
+    2 GiB (reads 2 GiB, writes 2 GiB) to calibrate the byte counters."""
+    import torch
+
+    from ftlm_inputs import graphs
+    from paper_2605_26261_amd import ftlm
+
+    dev = torch.device("cuda:0")
+    g = ftlm.Graph(N_SITES, graphs.icosidodecahedron())
+    for mode in (ftlm.CLT, ftlm.CR):
+        sec = ftlm.Sector(N_SITES, N_UP, mode, device=dev)
+        ftlm.lanczos(sec, g, SEED, 0, R, 3, ftlm.GAUSS, ftlm.F32)
+        x = torch.randn(sec.dim, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            ftlm.hv(sec, g, x, y)
+        torch.cuda.synchronize()
+        del sec, x, y
+        torch.cuda.empty_cache()
+    a = torch.empty(512 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("profile run done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="short kernel-only run for rocprofv3 counter passes")
     args = ap.parse_args()
+    if args.profile_kernels:
+        profile_kernels()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (use --gpus 1)",
               file=sys.stderr)

@@ -228,17 +228,15 @@ int ftlm_graph_create(int n_sites, int n_bonds, const int32_t* bi, const int32_t
     double jsum = 0.0;
     for (int s = 0; s < nb; ++s) {
         const int b = order[size_t(s)];
-        T.lo[s] = uint8_t(g->bi[size_t(b)]);
-        T.hi[s] = uint8_t(g->bj[size_t(b)]);
-        T.orig[s] = uint8_t(b);
+        T.pack[s] = uint32_t(g->bi[size_t(b)]) | (uint32_t(g->bj[size_t(b)]) << 8) | (uint32_t(b) << 16);
         T.coef_d[s] = 0.5 * g->J[size_t(b)];
         T.coef_f[s] = float(0.5 * g->J[size_t(b)]);
         jsum += g->J[size_t(b)];
     }
     for (int p = 0; p <= kMaxSites; ++p) {
         int c = 0;
-        for (int s = 0; s < nb; ++s) c += (T.lo[s] >= p) ? 1 : 0;
-        T.ends[p] = uint16_t(p < n_sites ? c : 0);
+        for (int s = 0; s < nb; ++s) c += (int(T.pack[s] & 0xffu) >= p) ? 1 : 0;
+        T.ends[p] = uint32_t(p < n_sites ? c : 0);
     }
     T.jsum4_d = 0.25 * jsum;
     T.jsum4_f = float(0.25 * jsum);

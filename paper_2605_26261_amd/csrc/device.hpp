@@ -83,22 +83,25 @@ __device__ __forceinline__ uint32_t clt_lookup(const CltEntry* clt, uint32_t n) 
     return e.prefix + __popc(e.mask & ((1u << j) - 1u));
 }
 
-// Bonds as the kernels see them (passed by value as a kernel argument, so
-// every read is a wave-uniform scalar load): sorted by their lower site,
-// highest first, so the combinatorial-ranking pass, which walks the sites
-// from the top, meets each bond at its lower site after its upper site is
-// known. The bonds with lower site >= p are the first ends[p] entries.
+// Bonds as the kernels see them, passed by value as a kernel argument.
+// Every field is a 32-bit word so that each read is a scalar (s_load_dword)
+// load: gfx9 has no scalar byte loads, and a vector load of bond data would
+// make each bond wait on the gathers still in flight. Bonds are sorted by
+// their lower site, highest first, so the combinatorial-ranking pass, which
+// walks the sites from the top, meets each bond at its lower site after its
+// upper site is known. The bonds with lower site >= p are the first ends[p].
 struct BondTable {
-    uint8_t lo[kMaxBonds];
-    uint8_t hi[kMaxBonds];
-    uint8_t orig[kMaxBonds];   // position of the bond in the caller's order
+    uint32_t pack[kMaxBonds];  // lo | hi << 8 | (position in the caller's order) << 16
     float coef_f[kMaxBonds];   // J_b / 2 (Eqs. 13-14 at s = 1/2)
     double coef_d[kMaxBonds];
-    uint16_t ends[kMaxSites + 1];
+    uint32_t ends[kMaxSites + 1];
     int n_bonds;
     int n_sites;
     float jsum4_f;   // sum_b J_b / 4: the diagonal when every bond is parallel
     double jsum4_d;
+    __device__ __forceinline__ uint32_t lo(int b) const { return pack[b] & 0xffu; }
+    __device__ __forceinline__ uint32_t hi(int b) const { return (pack[b] >> 8) & 0xffu; }
+    __device__ __forceinline__ uint32_t orig(int b) const { return pack[b] >> 16; }
 };
 
 // Visits one row t of the sector: finds its label n_t and, for every bond,
@@ -128,9 +131,9 @@ __device__ __forceinline__ L visit_row(uint32_t t, int n_up, const BondTable& B,
     if constexpr (MODE == kModeClt) {
         const uint32_t n = basis[t];
         for (int b = 0; b < B.n_bonds; ++b) {
-            const uint32_t si = (n >> B.lo[b]) & 1u, sj = (n >> B.hi[b]) & 1u;
+            const uint32_t si = (n >> B.lo(b)) & 1u, sj = (n >> B.hi(b)) & 1u;
             if (si != sj) {
-                const uint32_t m = n ^ ((1u << B.lo[b]) | (1u << B.hi[b]));
+                const uint32_t m = n ^ ((1u << B.lo(b)) | (1u << B.hi(b)));
                 const CltEntry e = clt[m >> 5];
                 v.flip(b, e.prefix + __popc(e.mask & ((1u << (m & 31u)) - 1u)));
             } else {
@@ -160,10 +163,11 @@ __device__ __forceinline__ L visit_row(uint32_t t, int n_up, const BondTable& B,
                 Y = c0 - Es;
             }
             ylds[p * 64] = Y;
-            const int end = B.ends[p];
+            const int end = int(B.ends[p]);
             for (; b < end; ++b) {
-                const uint32_t shi = uint32_t((n >> B.hi[b]) & 1);
-                if (shi != uint32_t(one)) v.flip(b, t + X + ylds[B.hi[b] * 64]);
+                const uint32_t hb = B.hi(b);
+                const uint32_t shi = uint32_t((n >> hb) & 1);
+                if (shi != uint32_t(one)) v.flip(b, t + X + ylds[hb * 64]);
                 else v.par(b);
             }
         }

@@ -112,56 +112,69 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, Hv
     T* __restrict__ y = static_cast<T*>(h.y);
     const T jsum4 = sizeof(T) == 4 ? T(B.jsum4_f) : T(B.jsum4_d);
 
-    T a_c[VB], b_c[VB];
-    double part[VB];
-#pragma unroll
-    for (int c = 0; c < VB; ++c) {
-        part[c] = 0.0;
-        if constexpr (EPI == kEpiLanczos) {
-            const Chain ch = h.chains[h.col0 + c];
-            a_c[c] = T(ch.s_cur);
-            b_c[c] = h.first ? T(0) : T(ch.beta_prev * ch.s_prev);
-        }
+    // Lanczos scalars of this block's columns (wave-uniform).
+    const Chain* chains = h.chains + h.col0;
+    if constexpr (EPI == kEpiLanczos) {
+        // per-wave running FP64 sums of <u_k, w> per column, in LDS
+        for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) red[i] = 0.0;
+        __syncthreads();
     }
 
     const uint32_t ntiles = (h.nrows + kBlock - 1) / kBlock;
     for_each_tile(ntiles, [&](uint32_t tile) {
         const uint32_t r = tile * kBlock + threadIdx.x;
-        if (r >= h.nrows) return;
-        const uint32_t t = h.row0 + r;
-        T acc[VB];
-#pragma unroll
-        for (int c = 0; c < VB; ++c) acc[c] = T(0);
-        T anti = T(0);
-        GatherVisitor<T, VB> vis{x, h.ld, h.col0, S.dim - 1, B, acc, anti};
-        visit_row<L, MODE>(t, S.n_up, B, C, S.basis, S.clt, ylds, vis);
+        const bool valid = r < h.nrows;
         T xt[VB], out[VB];
-        load_row<T, VB>(x + uint64_t(t) * h.ld + h.col0, xt);
-        const T diag = jsum4 - anti;
+        if (valid) {
+            const uint32_t t = h.row0 + r;
+            T acc[VB];
 #pragma unroll
-        for (int c = 0; c < VB; ++c) out[c] = diag * xt[c] + acc[c];
-        T* yrow = y + uint64_t(r) * h.ld + h.col0;
-        if constexpr (EPI == kEpiLanczos) {
-            T z[VB];
-            if (!h.first) {
-                load_row<T, VB>(yrow, z);
-            } else {
+            for (int c = 0; c < VB; ++c) acc[c] = T(0);
+            T anti = T(0);
+            GatherVisitor<T, VB> vis{x, h.ld, h.col0, S.dim - 1, B, acc, anti};
+            visit_row<L, MODE>(t, S.n_up, B, C, S.basis, S.clt, ylds, vis);
+            load_row<T, VB>(x + uint64_t(t) * h.ld + h.col0, xt);
+            const T diag = jsum4 - anti;
 #pragma unroll
-                for (int c = 0; c < VB; ++c) z[c] = T(0);
+            for (int c = 0; c < VB; ++c) out[c] = diag * xt[c] + acc[c];
+            T* yrow = y + uint64_t(r) * h.ld + h.col0;
+            if constexpr (EPI == kEpiLanczos) {
+                T z[VB];
+                if (!h.first) {
+                    load_row<T, VB>(yrow, z);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < VB; ++c) z[c] = T(0);
+                }
+#pragma unroll
+                for (int c = 0; c < VB; ++c) {
+                    const T a = sizeof(T) == 4 ? T(chains[c].hv_a_f) : T(chains[c].hv_a_d);
+                    const T b = sizeof(T) == 4 ? T(chains[c].hv_b_f) : T(chains[c].hv_b_d);
+                    out[c] = a * out[c] - b * z[c];
+                }
             }
+            store_row<T, VB>(yrow, out);
+        }
+        if constexpr (EPI == kEpiLanczos) {
+            // fold this tile's <u_k, w> terms into the wave's running sums
+            // (every lane takes part in the butterfly; rows past the end add 0)
 #pragma unroll
             for (int c = 0; c < VB; ++c) {
-                out[c] = a_c[c] * out[c] - b_c[c] * z[c];
-                part[c] += double(xt[c]) * double(out[c]);
+                double p = valid ? double(xt[c]) * double(out[c]) : 0.0;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off, 64);
+                if (lane == 0) red[wave * VB + c] += p;
             }
         }
-        store_row<T, VB>(yrow, out);
     });
 
     if constexpr (EPI == kEpiLanczos) {
-        block_sum<VB>(part, red);
-        if (threadIdx.x < VB)
-            h.partials[size_t(blockIdx.x) * h.pstride + h.col0 + threadIdx.x] = red[kWaves * VB + threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x < VB) {
+            double s = 0.0;
+            for (int w = 0; w < kWaves; ++w) s += red[w * VB + threadIdx.x];
+            h.partials[size_t(blockIdx.x) * h.pstride + h.col0 + threadIdx.x] = s;
+        }
         __shared__ int flag;
         if (last_block(h.ticket, &flag)) {
             for (int c = 0; c < VB; ++c) {
@@ -169,6 +182,8 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, Hv
                 if (threadIdx.x == 0) {
                     Chain* ch = &h.chains[h.col0 + c];
                     ch->alpha = ch->s_cur * tot;
+                    ch->up_d = ch->alpha * ch->s_cur;
+                    ch->up_f = float(ch->up_d);
                 }
             }
             if (threadIdx.x == 0) *h.ticket = 0u;

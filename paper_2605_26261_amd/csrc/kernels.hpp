@@ -22,9 +22,24 @@ struct Chain {
     double amax;       // max_{j<=k}(|alpha_j|, beta_{j-1}) for the stopping rule
     double alpha;      // alpha_k of the step in flight
     double norm;       // |u_1| of the start vector
+    // Scalars of the next kernels, precomputed once per step by the last
+    // workgroup of the previous kernel so that every thread reads them with
+    // scalar loads (no per-thread FP64 work or conversion):
+    //   H.x epilogue  w = hv_a * (H u_k) - hv_b * u_{k-1}
+    //   update        u_{k+1} = w - up * u_k
+    double hv_a_d, hv_b_d, up_d;
+    float hv_a_f, hv_b_f, up_f, pad_f;
     int32_t active;
     int32_t steps;
 };
+
+// Sets the next-step scalars of a chain from its FP64 state.
+__device__ __forceinline__ void chain_set_hv(Chain* ch) {
+    ch->hv_a_d = ch->s_cur;
+    ch->hv_b_d = ch->beta_prev * ch->s_prev;
+    ch->hv_a_f = float(ch->hv_a_d);
+    ch->hv_b_f = float(ch->hv_b_d);
+}
 
 // A sector as the kernels see it.
 struct SectorDev {

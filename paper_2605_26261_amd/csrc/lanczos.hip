@@ -76,6 +76,7 @@ __global__ __launch_bounds__(kBlock) void start_kernel(SectorDev S, StartLaunch 
                 ch->alpha = 0.0;
                 ch->active = nrm > 0.0 ? 1 : 0;
                 ch->steps = 0;
+                chain_set_hv(ch);
             }
         }
         if (threadIdx.x == 0) *a.ticket = 0u;
@@ -95,14 +96,10 @@ __global__ __launch_bounds__(kBlock) void update_kernel(SectorDev S, UpdateLaunc
     __shared__ int flag;
     const T* __restrict__ u = static_cast<const T*>(a.u);
     T* __restrict__ w = static_cast<T*>(a.w);
-    T coef[VB];
+    const Chain* chains = a.chains + a.col0;
     double part[VB];
 #pragma unroll
-    for (int c = 0; c < VB; ++c) {
-        const Chain ch = a.chains[a.col0 + c];
-        coef[c] = T(ch.alpha * ch.s_cur);
-        part[c] = 0.0;
-    }
+    for (int c = 0; c < VB; ++c) part[c] = 0.0;
     const uint32_t ntiles = (S.dim + kBlock - 1) / kBlock;
     for_each_tile(ntiles, [&](uint32_t tile) {
         const uint32_t t = tile * kBlock + threadIdx.x;
@@ -113,7 +110,8 @@ __global__ __launch_bounds__(kBlock) void update_kernel(SectorDev S, UpdateLaunc
         load_row<T, VB>(wrow, ww);
 #pragma unroll
         for (int c = 0; c < VB; ++c) {
-            ww[c] = ww[c] - coef[c] * uu[c];
+            const T coef = sizeof(T) == 4 ? T(chains[c].up_f) : T(chains[c].up_d);
+            ww[c] = ww[c] - coef * uu[c];
             part[c] += double(ww[c]) * double(ww[c]);
         }
         store_row<T, VB>(wrow, ww);
@@ -145,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(SectorDev S, UpdateLaunc
                         ch->s_cur = 1.0 / bk;
                         ch->beta_prev = bk;
                     }
+                    chain_set_hv(ch);
                 }
             }
         }

@@ -116,8 +116,8 @@ __global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDev S, const uin
 struct NeighborVisitor {
     uint64_t* out;
     const BondTable& B;
-    __device__ __forceinline__ void flip(int b, uint32_t idx) { out[B.orig[b]] = idx; }
-    __device__ __forceinline__ void par(int b) { out[B.orig[b]] = ~uint64_t(0); }
+    __device__ __forceinline__ void flip(int b, uint32_t idx) { out[B.orig(b)] = idx; }
+    __device__ __forceinline__ void par(int b) { out[B.orig(b)] = ~uint64_t(0); }
 };
 
 template <typename L, int MODE>
