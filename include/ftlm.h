@@ -198,6 +198,41 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
                  int M, int dist, int dtype, void* work_dev, size_t work_bytes, double* alpha_host,
                  double* beta_host, int32_t* steps_host, void* stream);
 
+/* ---- batched all-sector plans ---------------------------------------------
+ * A plan runs R Lanczos chains in each of several S^z sectors of one graph
+ * (for example every sector M >= 0) with one launch per kernel per Lanczos
+ * step covering all sectors: each sector owns a contiguous range of
+ * workgroups sized by its dimension (sectors of dimension 1 to 10^6+ in the
+ * same launch), and the M-step loop can be captured once in a HIP graph and
+ * replayed. Per-chain results are bitwise the same as ftlm_lanczos on the
+ * sector alone (the reduction order of a sector depends only on D).
+ *
+ * ftlm_plan_workspace_bytes: device bytes of the arena for the sectors
+ * n_ups[0..n_sectors-1] (1 <= n_sectors <= 65): sector tables, two [D][R]
+ * vector blocks per sector, reduction partials and chain states. */
+typedef struct ftlm_plan ftlm_plan;
+int ftlm_plan_workspace_bytes(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, int mode,
+                              int R, int dtype, size_t* bytes);
+
+/* ftlm_plan_create: lays the plan out in the caller's arena (256-byte
+ * aligned, at least ftlm_plan_workspace_bytes) and builds every sector's
+ * tables on `stream` (synchronizes). M is the number of Lanczos steps per
+ * chain (each sector stops at min(M, D_s) or on breakdown, as in
+ * ftlm_lanczos). */
+int ftlm_plan_create(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, int mode, int R, int M,
+                     int dtype, void* arena_dev, size_t arena_bytes, void* stream, ftlm_plan** out);
+
+/* ftlm_plan_run: draws the start vectors (sample r0 + r of each sector, as
+ * ftlm_start_vectors), runs the M Lanczos steps of all chains of all sectors
+ * and copies the coefficients to the host (synchronizes): alpha_host and
+ * beta_host are [n_sectors][R][M], steps_host [n_sectors][R]. With
+ * use_graph != 0 the step loop is captured into a HIP graph on first use and
+ * replayed; otherwise every kernel is launched eagerly. Work is ordered after
+ * the work already enqueued on `stream`. */
+int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_graph, double* alpha_host,
+                  double* beta_host, int32_t* steps_host, void* stream);
+void ftlm_plan_destroy(ftlm_plan* p);
+
 /* ---- Ritz values and the thermal reduction (host, FP64) --------------------
  * ftlm_ritz: eigenvalues theta[m] (ascending) of the m x m symmetric
  * tridiagonal T with diagonal alpha[0..m-1] and off-diagonal beta[0..m-2],

@@ -115,8 +115,7 @@ struct HvTimer {
 // ---- column chunking of a [D][ld] block --------------------------------------
 // Splits columns [0, nvec) into kernel widths, widest first, keeping every
 // vector access naturally aligned (ld, col0 and the base pointers).
-std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype,
-                                               std::initializer_list<const void*> ptrs) {
+std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtype, const std::vector<const void*>& ptrs) {
     const size_t es = dtype == FTLM_F32 ? 4 : 8;
     static const int w32[] = {32, 20, 16, 8, 4, 2, 1};
     static const int w64[] = {16, 8, 4, 2, 1};
@@ -142,37 +141,190 @@ std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype,
     return out;
 }
 
+std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype,
+                                               std::initializer_list<const void*> ptrs) {
+    return column_chunks_v(nvec, ld, dtype, std::vector<const void*>(ptrs));
+}
+
 int check_dtype(int dtype) {
     if (dtype != FTLM_F32 && dtype != FTLM_F64) return fail(FTLM_E_INVALID, "dtype %d is not FTLM_F32/FTLM_F64", dtype);
     return FTLM_OK;
 }
 
-// ---- Lanczos workspace layout -------------------------------------------------
-constexpr int kMaxSteps = 4096;
-constexpr int kMaxChains = 64;
-constexpr int kTickets = 64;
+// ---- Lanczos state layout -----------------------------------------------------
+constexpr int kTicketsPerSector = 1;
 
-struct WorkLayout {
-    size_t u0, u1, partials, chains, alpha, beta, tickets, total;
+// Byte offsets of one sector's Lanczos state inside a workspace or arena.
+struct SectorState {
+    size_t u0, u1, partials, chains, alpha, beta, ticket, keys;
 };
 
-WorkLayout work_layout(uint64_t dim, int R, int dtype) {
+// Lays out the state of a sector of dimension `dim` at `off`; returns the end.
+size_t layout_state(uint64_t dim, int R, int dtype, size_t off, SectorState& st) {
     const size_t es = dtype == FTLM_F32 ? 4 : 8;
-    WorkLayout w{};
-    size_t off = 0;
-    w.u0 = off; off = align256(off + size_t(dim) * size_t(R) * es);
-    w.u1 = off; off = align256(off + size_t(dim) * size_t(R) * es);
-    w.partials = off; off = align256(off + size_t(rows_grid(uint32_t(dim))) * size_t(R) * sizeof(double));
-    w.chains = off; off = align256(off + size_t(R) * sizeof(Chain));
-    w.alpha = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
-    w.beta = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
-    w.tickets = off; off = align256(off + kTickets * sizeof(uint32_t));
-    w.total = off;
-    return w;
+    st.u0 = off; off = align256(off + size_t(dim) * size_t(R) * es);
+    st.u1 = off; off = align256(off + size_t(dim) * size_t(R) * es);
+    st.partials = off; off = align256(off + size_t(rows_grid(uint32_t(dim))) * size_t(R) * sizeof(double));
+    st.chains = off; off = align256(off + size_t(R) * sizeof(Chain));
+    st.alpha = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
+    st.beta = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
+    st.ticket = off; off = align256(off + kTicketsPerSector * sizeof(uint32_t));
+    st.keys = off; off = align256(off + size_t(R) * sizeof(uint64_t));
+    return off;
 }
 
 template <typename P>
 P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(base) + off); }
+
+// A batch of R chains in each of a list of sectors (one sector for
+// ftlm_lanczos, all sectors of a plan), with the device descriptors of the
+// multi-sector Lanczos kernels. Host copies stay alive until the stream work
+// that reads them has been synchronized.
+struct LanczosJob {
+    int nsec = 0, R = 0, dtype = 0, mode = 0, n_sites = 0, grid = 0;
+    size_t lds = 0;
+    std::vector<SecWork> secs;           // host copies of the descriptors
+    std::vector<uint64_t> keys;          // [nsec][R] stream keys of the run
+    SecWork* dev_secs = nullptr;
+    uint64_t* dev_keys = nullptr;        // first sector's key block; sector s at dev_keys_of[s]
+    std::vector<uint64_t*> key_ptrs;
+    std::vector<std::pair<int, int>> chunks;
+    int max_steps = 0;                   // largest m_eff over the sectors
+
+    LanczosLaunch launch() const {
+        LanczosLaunch a{};
+        a.secs = dev_secs;
+        a.nsec = nsec;
+        a.grid = grid;
+        a.ld = uint64_t(R);
+        a.dtype = dtype;
+        a.eps = dtype == FTLM_F32 ? 1e-6 : 1e-12;
+        a.mode = mode;
+        a.n_sites = n_sites;
+        return a;
+    }
+};
+
+// Fills job.secs for sectors whose tables are described by `devs` and whose
+// state sits at `states` inside `base`; the descriptor array goes to
+// `dev_secs` (device). Blocks: each sector gets rows_grid(D) blocks starting
+// at a multiple of 8.
+void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::vector<SectorState>& states,
+                void* base, int R, int M, int dtype, SecWork* dev_secs) {
+    job.nsec = int(devs.size());
+    job.R = R;
+    job.dtype = dtype;
+    job.mode = devs[0].mode;
+    job.n_sites = devs[0].n_sites;
+    job.dev_secs = dev_secs;
+    job.secs.assign(devs.size(), SecWork{});
+    job.key_ptrs.clear();
+    uint32_t block = 0;
+    size_t lds = 0;
+    job.max_steps = 0;
+    for (size_t i = 0; i < devs.size(); ++i) {
+        SecWork& w = job.secs[i];
+        const SectorState& st = states[i];
+        w.S = devs[i];
+        w.u[0] = at<void>(base, st.u0);
+        w.u[1] = at<void>(base, st.u1);
+        w.chains = at<Chain>(base, st.chains);
+        w.partials = at<double>(base, st.partials);
+        w.ticket = at<uint32_t>(base, st.ticket);
+        w.alpha = at<double>(base, st.alpha);
+        w.beta = at<double>(base, st.beta);
+        w.keys = at<uint64_t>(base, st.keys);
+        job.key_ptrs.push_back(at<uint64_t>(base, st.keys));
+        w.G = rows_grid(devs[i].dim);
+        w.block0 = block;
+        block = (block + w.G + 7) & ~7u;
+        w.m_eff = int(std::min<uint64_t>(uint64_t(M), devs[i].dim));
+        job.max_steps = std::max(job.max_steps, w.m_eff);
+        lds = std::max(lds, hv_lds_bytes(devs[i]));
+    }
+    job.grid = int(block);
+    job.lds = lds;
+    std::vector<const void*> ptrs;
+    for (auto& w : job.secs) {
+        ptrs.push_back(w.u[0]);
+        ptrs.push_back(w.u[1]);
+    }
+    job.chunks = column_chunks_v(R, uint64_t(R), dtype, ptrs);
+}
+
+// Start vectors of samples r0 .. r0 + R - 1 in every sector of the job.
+int job_start(LanczosJob& job, uint64_t seed, uint64_t r0, int dist, hipStream_t st) {
+    job.keys.resize(size_t(job.nsec) * size_t(job.R));
+    for (int s = 0; s < job.nsec; ++s) {
+        job.secs[size_t(s)].r0 = r0;
+        for (int c = 0; c < job.R; ++c)
+            job.keys[size_t(s) * job.R + size_t(c)] = stream_key(seed, job.secs[size_t(s)].S.n_up, r0 + uint64_t(c));
+    }
+    HIP_CHECK(hipMemcpyAsync(job.dev_secs, job.secs.data(), job.secs.size() * sizeof(SecWork),
+                             hipMemcpyHostToDevice, st));
+    for (int s = 0; s < job.nsec; ++s)
+        HIP_CHECK(hipMemcpyAsync(job.key_ptrs[size_t(s)], job.keys.data() + size_t(s) * job.R,
+                                 size_t(job.R) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    LanczosLaunch a = job.launch();
+    a.dist = dist;
+    HIP_CHECK(launch_chain_init(a, st));
+    for (int c = 0; c < job.R; c += 4) {
+        a.col0 = uint32_t(c);
+        a.vb = std::min(4, job.R - c);
+        HIP_CHECK(launch_start(a, st));
+    }
+    return FTLM_OK;
+}
+
+// Lanczos steps 1..job.max_steps for every chunk of columns.
+int job_steps(const LanczosJob& job, const BondTable& B, hipStream_t st, bool timed = true) {
+    LanczosLaunch a = job.launch();
+    for (int k = 1; k <= job.max_steps; ++k) {
+        a.step = k;
+        for (auto [col, vb] : job.chunks) {
+            a.col0 = uint32_t(col);
+            a.vb = vb;
+            if (timed) {
+                HvTimer timer(st);
+                HIP_CHECK(launch_hv_lanczos(B, a, job.lds, st));
+            } else {
+                HIP_CHECK(launch_hv_lanczos(B, a, job.lds, st));
+            }
+            HIP_CHECK(launch_update(a, st));
+        }
+    }
+    return FTLM_OK;
+}
+
+// Copies sector s's coefficients into [R][M] host arrays (after a sync).
+int job_collect(const LanczosJob& job, int M, double* alpha_host, double* beta_host, int32_t* steps_host,
+                hipStream_t st) {
+    const size_t R = size_t(job.R);
+    std::vector<double> a(size_t(job.nsec) * R * kMaxSteps), b(a.size());
+    std::vector<Chain> ch(size_t(job.nsec) * R);
+    for (int s = 0; s < job.nsec; ++s) {
+        const SecWork& w = job.secs[size_t(s)];
+        HIP_CHECK(hipMemcpyAsync(a.data() + size_t(s) * R * kMaxSteps, w.alpha, R * kMaxSteps * sizeof(double),
+                                 hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipMemcpyAsync(b.data() + size_t(s) * R * kMaxSteps, w.beta, R * kMaxSteps * sizeof(double),
+                                 hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipMemcpyAsync(ch.data() + size_t(s) * R, w.chains, R * sizeof(Chain), hipMemcpyDeviceToHost, st));
+    }
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int s = 0; s < job.nsec; ++s) {
+        for (size_t r = 0; r < R; ++r) {
+            const Chain& c = ch[size_t(s) * R + r];
+            const size_t row = size_t(s) * R + r;
+            steps_host[row] = c.steps;
+            for (int k = 0; k < M; ++k) {
+                const bool in = k < c.steps;
+                alpha_host[row * size_t(M) + size_t(k)] = in ? a[row * kMaxSteps + size_t(k)] : 0.0;
+                beta_host[row * size_t(M) + size_t(k)] = in ? b[row * kMaxSteps + size_t(k)] : 0.0;
+            }
+        }
+    }
+    return FTLM_OK;
+}
 
 }  // namespace
 
@@ -376,8 +528,7 @@ int ftlm_hv_rows(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, v
     h.row0 = uint32_t(row0);
     h.nrows = uint32_t(nrows);
     h.dtype = dtype;
-    h.epi = kEpiPlain;
-    h.grid = rows_grid(uint32_t(nrows));
+    h.grid = int(rows_grid(uint32_t(nrows)));
     for (auto [col, vb] : column_chunks(nvec, uint64_t(nvec), dtype, {x_dev, y_dev})) {
         h.col0 = uint32_t(col);
         h.vb = vb;
@@ -394,37 +545,22 @@ int ftlm_hv(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, void* 
 }
 
 // ---- start vectors and Lanczos ----------------------------------------------------
-int ftlm_lanczos_workspace_bytes(const ftlm_sector* s, int R, int dtype, size_t* bytes) {
-    if (!s || !bytes) return fail(FTLM_E_INVALID, "null argument");
-    if (int rc = check_dtype(dtype)) return rc;
-    if (R < 1 || R > kMaxChains) return fail(FTLM_E_RANGE, "R %d not in [1, %d]", R, kMaxChains);
-    *bytes = work_layout(s->dim, R, dtype).total;
-    return ok();
-}
-
+// Single-sector workspace: the sector's Lanczos state followed by its device
+// descriptor.
 namespace {
 
-int enqueue_start(const ftlm_sector* s, uint64_t seed, uint64_t r0, int R, int dist, int dtype, void* q,
-                  void* work, const WorkLayout& wl, hipStream_t st) {
-    StartLaunch a{};
-    a.q = q;
-    a.ld = uint64_t(R);
-    a.col0 = 0;
-    a.ncols = R;
-    a.dtype = dtype;
-    a.dist = dist;
-    for (int c = 0; c < R; ++c) {
-        a.keys[c] = stream_key(seed, s->n_up, r0 + uint64_t(c));
-        a.sample[c] = r0 + uint64_t(c);
-    }
-    a.grid = rows_grid(uint32_t(s->dim));
-    a.pstride = R;
-    a.chains = at<Chain>(work, wl.chains);
-    a.partials = at<double>(work, wl.partials);
-    a.ticket = at<uint32_t>(work, wl.tickets);
-    HIP_CHECK(launch_chain_init(a.chains, R, a.ticket, kTickets, st));
-    HIP_CHECK(launch_start(s->dev, a, st));
-    return FTLM_OK;
+struct SingleLayout {
+    SectorState st;
+    size_t secs, total;
+};
+
+SingleLayout single_layout(uint64_t dim, int R, int dtype) {
+    SingleLayout l{};
+    size_t off = layout_state(dim, R, dtype, 0, l.st);
+    l.secs = off;
+    off = align256(off + sizeof(SecWork));
+    l.total = off;
+    return l;
 }
 
 int check_lanczos_args(const ftlm_sector* s, int R, int dist, int dtype, void* work, size_t work_bytes) {
@@ -432,24 +568,38 @@ int check_lanczos_args(const ftlm_sector* s, int R, int dist, int dtype, void* w
     if (int rc = check_dtype(dtype)) return rc;
     if (dist != FTLM_PM1 && dist != FTLM_GAUSS && dist != FTLM_UNIT) return fail(FTLM_E_INVALID, "bad dist %d", dist);
     if (R < 1 || R > kMaxChains) return fail(FTLM_E_RANGE, "R %d not in [1, %d]", R, kMaxChains);
-    const size_t need = work_layout(s->dim, R, dtype).total;
+    const size_t need = single_layout(s->dim, R, dtype).total;
     if (work_bytes < need) return fail(FTLM_E_NOSPACE, "workspace holds %zu bytes, %zu needed", work_bytes, need);
     if (reinterpret_cast<uintptr_t>(work) % 256 != 0) return fail(FTLM_E_INVALID, "workspace not 256-byte aligned");
     return FTLM_OK;
 }
 
+void single_job(LanczosJob& job, const ftlm_sector* s, int R, int M, int dtype, void* work) {
+    const SingleLayout l = single_layout(s->dim, R, dtype);
+    job_layout(job, {s->dev}, {l.st}, work, R, M, dtype, at<SecWork>(work, l.secs));
+}
+
 }  // namespace
+
+int ftlm_lanczos_workspace_bytes(const ftlm_sector* s, int R, int dtype, size_t* bytes) {
+    if (!s || !bytes) return fail(FTLM_E_INVALID, "null argument");
+    if (int rc = check_dtype(dtype)) return rc;
+    if (R < 1 || R > kMaxChains) return fail(FTLM_E_RANGE, "R %d not in [1, %d]", R, kMaxChains);
+    *bytes = single_layout(s->dim, R, dtype).total;
+    return ok();
+}
 
 int ftlm_start_vectors(const ftlm_sector* s, uint64_t seed, uint64_t r0, int R, int dist, int dtype, void* q_dev,
                        double* norms_host, void* work_dev, size_t work_bytes, void* stream) {
     if (int rc = check_lanczos_args(s, R, dist, dtype, work_dev, work_bytes)) return rc;
     if (!q_dev || !norms_host) return fail(FTLM_E_INVALID, "null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const WorkLayout wl = work_layout(s->dim, R, dtype);
-    if (int rc = enqueue_start(s, seed, r0, R, dist, dtype, q_dev, work_dev, wl, st)) return rc;
+    LanczosJob job;
+    single_job(job, s, R, 1, dtype, work_dev);
+    job.secs[0].u[0] = q_dev;  // the start block goes to the caller's buffer
+    if (int rc = job_start(job, seed, r0, dist, st)) return rc;
     std::vector<Chain> ch(static_cast<size_t>(R));
-    HIP_CHECK(hipMemcpyAsync(ch.data(), at<Chain>(work_dev, wl.chains), size_t(R) * sizeof(Chain),
-                             hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(ch.data(), job.secs[0].chains, size_t(R) * sizeof(Chain), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     for (int c = 0; c < R; ++c) norms_host[c] = ch[size_t(c)].norm;
     return ok();
@@ -463,72 +613,170 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
     if (g->n_sites != s->n_sites) return fail(FTLM_E_INVALID, "graph has %d sites, sector %d", g->n_sites, s->n_sites);
     if (M < 1 || M > kMaxSteps) return fail(FTLM_E_RANGE, "M %d not in [1, %d]", M, kMaxSteps);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const WorkLayout wl = work_layout(s->dim, R, dtype);
-    void* U[2] = {at<void>(work_dev, wl.u0), at<void>(work_dev, wl.u1)};
-    if (int rc = enqueue_start(s, seed, r0, R, dist, dtype, U[0], work_dev, wl, st)) return rc;
-    const int m_eff = int(std::min<uint64_t>(uint64_t(M), s->dim));
-    const int grid = rows_grid(uint32_t(s->dim));
-    const auto chunks = column_chunks(R, uint64_t(R), dtype, {U[0], U[1]});
-    HvLaunch h{};
-    h.ld = uint64_t(R);
-    h.row0 = 0;
-    h.nrows = uint32_t(s->dim);
-    h.dtype = dtype;
-    h.epi = kEpiLanczos;
-    h.pstride = R;
-    h.grid = grid;
-    h.chains = at<Chain>(work_dev, wl.chains);
-    h.partials = at<double>(work_dev, wl.partials);
-    h.ticket = at<uint32_t>(work_dev, wl.tickets);
-    UpdateLaunch u{};
-    u.ld = uint64_t(R);
-    u.dtype = dtype;
-    u.grid = grid;
-    u.pstride = R;
-    u.m_eff = m_eff;
-    u.eps = dtype == FTLM_F32 ? 1e-6 : 1e-12;
-    u.M = kMaxSteps;
-    u.chains = h.chains;
-    u.partials = h.partials;
-    u.ticket = h.ticket;
-    u.alpha = at<double>(work_dev, wl.alpha);
-    u.beta = at<double>(work_dev, wl.beta);
-    for (int k = 1; k <= m_eff; ++k) {
-        void* cur = U[(k - 1) & 1];
-        void* prev = U[k & 1];
-        h.x = cur;
-        h.y = prev;
-        h.first = k == 1 ? 1 : 0;
-        u.u = cur;
-        u.w = prev;
-        u.step = k;
-        for (auto [col, vb] : chunks) {
-            h.col0 = uint32_t(col);
-            h.vb = vb;
-            {
-                HvTimer timer(st);
-                HIP_CHECK(launch_hv(s->dev, g->table, h, st));
-            }
-            u.col0 = uint32_t(col);
-            u.ncols = vb;
-            HIP_CHECK(launch_update(s->dev, u, st));
-        }
-    }
-    std::vector<double> a(size_t(R) * kMaxSteps), b(size_t(R) * kMaxSteps);
-    std::vector<Chain> ch(static_cast<size_t>(R));
-    HIP_CHECK(hipMemcpyAsync(a.data(), u.alpha, a.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipMemcpyAsync(b.data(), u.beta, b.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipMemcpyAsync(ch.data(), h.chains, ch.size() * sizeof(Chain), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    for (int r = 0; r < R; ++r) {
-        steps_host[r] = ch[size_t(r)].steps;
-        for (int k = 0; k < M; ++k) {
-            const bool in = k < ch[size_t(r)].steps;
-            alpha_host[size_t(r) * M + size_t(k)] = in ? a[size_t(r) * kMaxSteps + size_t(k)] : 0.0;
-            beta_host[size_t(r) * M + size_t(k)] = in ? b[size_t(r) * kMaxSteps + size_t(k)] : 0.0;
-        }
-    }
+    LanczosJob job;
+    single_job(job, s, R, M, dtype, work_dev);
+    if (int rc = job_start(job, seed, r0, dist, st)) return rc;
+    if (int rc = job_steps(job, g->table, st)) return rc;
+    if (int rc = job_collect(job, M, alpha_host, beta_host, steps_host, st)) return rc;
     return ok();
+}
+
+// ---- batched all-sector plans ------------------------------------------------------
+}  // extern "C"
+
+struct ftlm_plan {
+    BondTable table{};
+    int n_sites = 0, mode = 0, R = 0, M = 0, dtype = 0;
+    std::vector<ftlm_sector*> sectors;
+    LanczosJob job;
+    hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~ftlm_plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ready) (void)hipEventDestroy(ready);
+        if (stream) (void)hipStreamDestroy(stream);
+        for (auto* s : sectors) delete s;
+    }
+};
+
+namespace {
+
+// Arena of a plan: the sector descriptors, then per sector its tables and its
+// Lanczos state.
+struct PlanLayout {
+    size_t secs;
+    std::vector<size_t> table;
+    std::vector<size_t> table_bytes;
+    std::vector<SectorState> state;
+    size_t total;
+};
+
+int plan_layout(int n_sites, int n_sectors, const int32_t* n_ups, int mode, int R, int dtype, PlanLayout& L) {
+    L = PlanLayout{};
+    size_t off = 0;
+    L.secs = off;
+    off = align256(off + size_t(n_sectors) * sizeof(SecWork));
+    for (int i = 0; i < n_sectors; ++i) {
+        size_t tb = 0;
+        if (int rc = ftlm_sector_table_bytes(n_sites, n_ups[i], mode, &tb)) return rc;
+        L.table.push_back(off);
+        L.table_bytes.push_back(tb);
+        off = align256(off + tb);
+        SectorState st{};
+        off = layout_state(binom_u64(n_sites, n_ups[i]), R, dtype, off, st);
+        L.state.push_back(st);
+    }
+    L.total = off;
+    return FTLM_OK;
+}
+
+int check_plan_args(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, int mode, int R, int dtype) {
+    if (!g || !n_ups) return fail(FTLM_E_INVALID, "null argument");
+    if (n_sectors < 1 || n_sectors > kMaxPlanSectors)
+        return fail(FTLM_E_RANGE, "n_sectors %d not in [1, %d]", n_sectors, kMaxPlanSectors);
+    if (int rc = check_dtype(dtype)) return rc;
+    if (R < 1 || R > kMaxChains) return fail(FTLM_E_RANGE, "R %d not in [1, %d]", R, kMaxChains);
+    for (int i = 0; i < n_sectors; ++i) {
+        if (n_ups[i] < 0 || n_ups[i] > g->n_sites) return fail(FTLM_E_INVALID, "n_ups[%d] = %d", i, n_ups[i]);
+        for (int j = 0; j < i; ++j)
+            if (n_ups[j] == n_ups[i]) return fail(FTLM_E_INVALID, "sector n_up = %d listed twice", n_ups[i]);
+    }
+    (void)mode;
+    return FTLM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ftlm_plan_workspace_bytes(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, int mode, int R, int dtype,
+                              size_t* bytes) {
+    if (!bytes) return fail(FTLM_E_INVALID, "null argument");
+    if (int rc = check_plan_args(g, n_sectors, n_ups, mode, R, dtype)) return rc;
+    PlanLayout L;
+    if (int rc = plan_layout(g->n_sites, n_sectors, n_ups, mode, R, dtype, L)) return rc;
+    *bytes = L.total;
+    return ok();
+}
+
+int ftlm_plan_create(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, int mode, int R, int M, int dtype,
+                     void* arena_dev, size_t arena_bytes, void* stream, ftlm_plan** out) {
+    if (!out || !arena_dev) return fail(FTLM_E_INVALID, "null argument");
+    *out = nullptr;
+    if (int rc = check_plan_args(g, n_sectors, n_ups, mode, R, dtype)) return rc;
+    if (M < 1 || M > kMaxSteps) return fail(FTLM_E_RANGE, "M %d not in [1, %d]", M, kMaxSteps);
+    if (reinterpret_cast<uintptr_t>(arena_dev) % 256 != 0) return fail(FTLM_E_INVALID, "arena not 256-byte aligned");
+    PlanLayout L;
+    if (int rc = plan_layout(g->n_sites, n_sectors, n_ups, mode, R, dtype, L)) return rc;
+    if (arena_bytes < L.total) return fail(FTLM_E_NOSPACE, "arena holds %zu bytes, %zu needed", arena_bytes, L.total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ftlm_plan* p = new ftlm_plan();
+    p->table = g->table;
+    p->n_sites = g->n_sites;
+    p->mode = mode;
+    p->R = R;
+    p->M = M;
+    p->dtype = dtype;
+    std::vector<SectorDev> devs;
+    for (int i = 0; i < n_sectors; ++i) {
+        ftlm_sector* s = nullptr;
+        int rc = ftlm_sector_create(g->n_sites, n_ups[i], mode, at<void>(arena_dev, L.table[size_t(i)]),
+                                    L.table_bytes[size_t(i)], stream, &s);
+        if (rc) {
+            delete p;
+            return rc;
+        }
+        p->sectors.push_back(s);
+        devs.push_back(s->dev);
+    }
+    job_layout(p->job, devs, L.state, arena_dev, R, M, dtype, at<SecWork>(arena_dev, L.secs));
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ready, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(FTLM_E_DEVICE, "plan setup: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return ok();
+}
+
+int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_graph, double* alpha_host,
+                  double* beta_host, int32_t* steps_host, void* stream) {
+    if (!p || !alpha_host || !beta_host || !steps_host) return fail(FTLM_E_INVALID, "null argument");
+    if (dist != FTLM_PM1 && dist != FTLM_GAUSS && dist != FTLM_UNIT) return fail(FTLM_E_INVALID, "bad dist %d", dist);
+    hipStream_t caller = static_cast<hipStream_t>(stream);
+    HIP_CHECK(hipEventRecord(p->ready, caller));
+    HIP_CHECK(hipStreamWaitEvent(p->stream, p->ready, 0));
+    if (int rc = job_start(p->job, seed, r0, dist, p->stream)) return rc;
+    if (use_graph) {
+        if (!p->exec) {
+            HIP_CHECK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+            const int rc = job_steps(p->job, p->table, p->stream, false);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(p->stream, &graph);
+            if (rc != FTLM_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(FTLM_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+            p->graph = graph;
+            HIP_CHECK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+        }
+        HIP_CHECK(hipGraphLaunch(p->exec, p->stream));
+    } else {
+        if (int rc = job_steps(p->job, p->table, p->stream)) return rc;
+    }
+    if (int rc = job_collect(p->job, p->M, alpha_host, beta_host, steps_host, p->stream)) return rc;
+    return ok();
+}
+
+void ftlm_plan_destroy(ftlm_plan* p) {
+    if (p && p->stream) (void)hipStreamSynchronize(p->stream);
+    delete p;
 }
 
 // ---- host FP64 -------------------------------------------------------------------

@@ -86,61 +86,60 @@ struct GatherVisitor {
     __device__ __forceinline__ void par(int) {}
 };
 
-__host__ __device__ constexpr size_t hv_red_bytes() { return kBlock * sizeof(double); }
-inline size_t hv_binom_lds_bytes(const SectorDev& s) {
-    return s.mode == kModeCr ? ((size_t(s.n_sites) * size_t(s.bw) * 4 + 15) & ~size_t(15)) : 0;
-}
-inline size_t hv_slab_lds_bytes(const SectorDev& s) {
-    return s.mode == kModeCr ? size_t(kWaves) * size_t(s.n_sites) * 64 * 4 : 0;
-}
-inline size_t hv_lds_bytes(const SectorDev& s) {
-    return hv_red_bytes() + hv_binom_lds_bytes(s) + hv_slab_lds_bytes(s);
-}
+// LDS layout shared by the H.x kernels: FP64 scratch (kBlock doubles), the
+// binomial table (CR), then one [site][lane] slab of Y values per wave (CR).
+struct HvLds {
+    double* red;
+    uint32_t* binom;
+    uint32_t* ylds;
+};
 
-template <typename L, int MODE, typename T, int VB, int EPI>
-__global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, HvLaunch h) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    double* red = reinterpret_cast<double*>(smem);
-    uint32_t* binom_lds = reinterpret_cast<uint32_t*>(smem + hv_red_bytes());
-    uint32_t* slabs = binom_lds + ((S.n_sites * S.bw + 3) & ~3);
-    if constexpr (MODE == kModeCr) stage_binomials(binom_lds, S.binom, S.n_sites * S.bw);
-    const Binom C{binom_lds, S.bw};
+template <int MODE>
+__device__ __forceinline__ HvLds hv_lds_setup(unsigned char* smem, const SectorDev& S) {
+    HvLds l;
+    l.red = reinterpret_cast<double*>(smem);
+    l.binom = reinterpret_cast<uint32_t*>(smem + hv_red_bytes());
+    uint32_t* slabs = l.binom + ((S.n_sites * S.bw + 3) & ~3);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t* ylds = slabs + wave * S.n_sites * 64 + lane;
+    l.ylds = slabs + wave * S.n_sites * 64 + lane;
+    if constexpr (MODE == kModeCr) stage_binomials(l.binom, S.binom, S.n_sites * S.bw);
+    return l;
+}
 
-    const T* __restrict__ x = static_cast<const T*>(h.x);
-    T* __restrict__ y = static_cast<T*>(h.y);
+// The rows of one block of a (sub-)grid of G blocks: y = H x on rows
+// [row0, row0 + nrows), columns [col0, col0 + VB) of [D][ld] blocks. In the
+// Lanczos epilogue y holds u_{k-1} on entry (unless `first`) and receives
+// w = hv_a (H u_k) - hv_b u_{k-1} per column; the products u_k[t] w[t] are
+// folded, tile by tile, into per-wave FP64 sums wsum[wave * VB + c] (LDS).
+template <typename L, int MODE, typename T, int VB, int EPI>
+__device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, const HvLds& lds,
+                                        const T* __restrict__ x, T* __restrict__ y, uint64_t ld,
+                                        uint32_t col0, uint32_t row0, uint32_t nrows, uint32_t bid,
+                                        uint32_t G, const Chain* chains, bool first, double* wsum) {
+    const Binom C{lds.binom, S.bw};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const T jsum4 = sizeof(T) == 4 ? T(B.jsum4_f) : T(B.jsum4_d);
-
-    // Lanczos scalars of this block's columns (wave-uniform).
-    const Chain* chains = h.chains + h.col0;
-    if constexpr (EPI == kEpiLanczos) {
-        // per-wave running FP64 sums of <u_k, w> per column, in LDS
-        for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) red[i] = 0.0;
-        __syncthreads();
-    }
-
-    const uint32_t ntiles = (h.nrows + kBlock - 1) / kBlock;
-    for_each_tile(ntiles, [&](uint32_t tile) {
+    const uint32_t ntiles = (nrows + kBlock - 1) / kBlock;
+    for_each_tile(ntiles, bid, G, [&](uint32_t tile) {
         const uint32_t r = tile * kBlock + threadIdx.x;
-        const bool valid = r < h.nrows;
+        const bool valid = r < nrows;
         T xt[VB], out[VB];
         if (valid) {
-            const uint32_t t = h.row0 + r;
+            const uint32_t t = row0 + r;
             T acc[VB];
 #pragma unroll
             for (int c = 0; c < VB; ++c) acc[c] = T(0);
             T anti = T(0);
-            GatherVisitor<T, VB> vis{x, h.ld, h.col0, S.dim - 1, B, acc, anti};
-            visit_row<L, MODE>(t, S.n_up, B, C, S.basis, S.clt, ylds, vis);
-            load_row<T, VB>(x + uint64_t(t) * h.ld + h.col0, xt);
+            GatherVisitor<T, VB> vis{x, ld, col0, S.dim - 1, B, acc, anti};
+            visit_row<L, MODE>(t, S.n_up, B, C, S.basis, S.clt, lds.ylds, vis);
+            load_row<T, VB>(x + uint64_t(t) * ld + col0, xt);
             const T diag = jsum4 - anti;
 #pragma unroll
             for (int c = 0; c < VB; ++c) out[c] = diag * xt[c] + acc[c];
-            T* yrow = y + uint64_t(r) * h.ld + h.col0;
+            T* yrow = y + uint64_t(r) * ld + col0;
             if constexpr (EPI == kEpiLanczos) {
                 T z[VB];
-                if (!h.first) {
+                if (!first) {
                     load_row<T, VB>(yrow, z);
                 } else {
 #pragma unroll
@@ -156,45 +155,72 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, Hv
             store_row<T, VB>(yrow, out);
         }
         if constexpr (EPI == kEpiLanczos) {
-            // fold this tile's <u_k, w> terms into the wave's running sums
-            // (every lane takes part in the butterfly; rows past the end add 0)
+            // every lane takes part in the butterfly; rows past the end add 0
 #pragma unroll
             for (int c = 0; c < VB; ++c) {
                 double p = valid ? double(xt[c]) * double(out[c]) : 0.0;
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off, 64);
-                if (lane == 0) red[wave * VB + c] += p;
+                if (lane == 0) wsum[wave * VB + c] += p;
             }
         }
     });
+}
 
-    if constexpr (EPI == kEpiLanczos) {
-        __syncthreads();
-        if (threadIdx.x < VB) {
-            double s = 0.0;
-            for (int w = 0; w < kWaves; ++w) s += red[w * VB + threadIdx.x];
-            h.partials[size_t(blockIdx.x) * h.pstride + h.col0 + threadIdx.x] = s;
-        }
-        __shared__ int flag;
-        if (last_block(h.ticket, &flag)) {
-            for (int c = 0; c < VB; ++c) {
-                const double tot = grid_sum_col(h.partials, int(gridDim.x), h.pstride, int(h.col0) + c, red);
-                if (threadIdx.x == 0) {
-                    Chain* ch = &h.chains[h.col0 + c];
-                    ch->alpha = ch->s_cur * tot;
-                    ch->up_d = ch->alpha * ch->s_cur;
-                    ch->up_f = float(ch->up_d);
-                }
+template <typename L, int MODE, typename T, int VB>
+__global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, HvLaunch h) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const HvLds lds = hv_lds_setup<MODE>(smem, S);
+    hv_body<L, MODE, T, VB, kEpiPlain>(S, B, lds, static_cast<const T*>(h.x), static_cast<T*>(h.y), h.ld, h.col0,
+                                        h.row0, h.nrows, blockIdx.x, gridDim.x, nullptr, false, nullptr);
+}
+
+// First half of Lanczos step k over every sector of the launch (one launch
+// serves one sector or all sectors of a plan): w = H q_k - beta_{k-1} q_{k-1}
+// and the FP64 partials of <u_k, w>; the last block of each sector sums the
+// partials in block order into alpha_k (and the update coefficient).
+template <typename L, int MODE, typename T, int VB>
+__global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(BondTable B, LanczosLaunch a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int flag;
+    uint32_t local = 0;
+    const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
+    if (s < 0) return;
+    const SecWork& sw = a.secs[s];
+    const SectorDev S = sw.S;
+    const HvLds lds = hv_lds_setup<MODE>(smem, S);
+    double* wsum = lds.red;
+    for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
+    __syncthreads();
+    const T* x = static_cast<const T*>(sw.u[(a.step - 1) & 1]);
+    T* y = static_cast<T*>(sw.u[a.step & 1]);
+    const Chain* chains = sw.chains + a.col0;
+    hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, chains,
+                                          a.step == 1, wsum);
+    __syncthreads();
+    if (threadIdx.x < VB) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += wsum[w * VB + threadIdx.x];
+        sw.partials[size_t(local) * a.ld + a.col0 + threadIdx.x] = t;
+    }
+    if (last_block(sw.ticket, sw.G, &flag)) {
+        for (int c = 0; c < VB; ++c) {
+            const double tot = grid_sum_col(sw.partials, int(sw.G), int(a.ld), int(a.col0) + c, lds.red);
+            if (threadIdx.x == 0) {
+                Chain* ch = &sw.chains[a.col0 + c];
+                ch->alpha = ch->s_cur * tot;
+                ch->up_d = ch->alpha * ch->s_cur;
+                ch->up_f = float(ch->up_d);
             }
-            if (threadIdx.x == 0) *h.ticket = 0u;
         }
+        if (threadIdx.x == 0) *sw.ticket = 0u;
     }
 }
 
-template <typename L, int MODE, typename T, int VB, int EPI>
+template <typename L, int MODE, typename T, int VB>
 hipError_t launch_hv_one(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st) {
     const size_t lds = hv_lds_bytes(s);
-    auto kern = hv_kernel<L, MODE, T, VB, EPI>;
+    auto kern = hv_kernel<L, MODE, T, VB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -204,37 +230,62 @@ hipError_t launch_hv_one(const SectorDev& s, const BondTable& B, const HvLaunch&
     return hipGetLastError();
 }
 
-template <typename L, int MODE, typename T, int EPI>
-hipError_t launch_hv_vb(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st) {
-    switch (h.vb) {
-        case 1: return launch_hv_one<L, MODE, T, 1, EPI>(s, B, h, st);
-        case 2: return launch_hv_one<L, MODE, T, 2, EPI>(s, B, h, st);
-        case 4: return launch_hv_one<L, MODE, T, 4, EPI>(s, B, h, st);
-        case 8: return launch_hv_one<L, MODE, T, 8, EPI>(s, B, h, st);
-        case 16: return launch_hv_one<L, MODE, T, 16, EPI>(s, B, h, st);
+template <typename L, int MODE, typename T, int VB>
+hipError_t launch_lanczos_one(const BondTable& B, const LanczosLaunch& a, size_t lds, hipStream_t st) {
+    auto kern = hv_lanczos_kernel<L, MODE, T, VB>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(unsigned(a.grid)), dim3(kBlock), lds, st, B, a);
+    return hipGetLastError();
+}
+
+// Dispatch over the vector-block width VB (columns per launch).
+template <typename T, typename F>
+hipError_t with_vb(int vb, F&& f) {
+    switch (vb) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 16: return f(std::integral_constant<int, 16>{});
         case 20:
-            if constexpr (sizeof(T) == 4) return launch_hv_one<L, MODE, T, 20, EPI>(s, B, h, st);
+            if constexpr (sizeof(T) == 4) return f(std::integral_constant<int, 20>{});
             else return hipErrorInvalidValue;
         case 32:
-            if constexpr (sizeof(T) == 4) return launch_hv_one<L, MODE, T, 32, EPI>(s, B, h, st);
+            if constexpr (sizeof(T) == 4) return f(std::integral_constant<int, 32>{});
             else return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
+// Dispatch over label width and indexing mode.
+template <typename F>
+hipError_t with_mode(int mode, int n_sites, F&& f) {
+    if (mode == kModeClt) return f(uint32_t{}, std::integral_constant<int, kModeClt>{});
+    if (n_sites > 32) return f(uint64_t{}, std::integral_constant<int, kModeCr>{});
+    return f(uint32_t{}, std::integral_constant<int, kModeCr>{});
+}
+
 template <typename T>
 hipError_t launch_hv_typed(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st) {
-    const bool wide = s.n_sites > 32;
-    if (s.mode == kModeClt) {
-        return h.epi == kEpiLanczos ? launch_hv_vb<uint32_t, kModeClt, T, kEpiLanczos>(s, B, h, st)
-                                    : launch_hv_vb<uint32_t, kModeClt, T, kEpiPlain>(s, B, h, st);
-    }
-    if (wide) {
-        return h.epi == kEpiLanczos ? launch_hv_vb<uint64_t, kModeCr, T, kEpiLanczos>(s, B, h, st)
-                                    : launch_hv_vb<uint64_t, kModeCr, T, kEpiPlain>(s, B, h, st);
-    }
-    return h.epi == kEpiLanczos ? launch_hv_vb<uint32_t, kModeCr, T, kEpiLanczos>(s, B, h, st)
-                                : launch_hv_vb<uint32_t, kModeCr, T, kEpiPlain>(s, B, h, st);
+    return with_mode(s.mode, s.n_sites, [&](auto l, auto m) {
+        using L = decltype(l);
+        return with_vb<T>(h.vb, [&](auto vb) { return launch_hv_one<L, decltype(m)::value, T, decltype(vb)::value>(s, B, h, st); });
+    });
+}
+
+template <typename T>
+hipError_t launch_lanczos_typed(int mode, int n_sites, const BondTable& B, const LanczosLaunch& a, size_t lds,
+                                hipStream_t st) {
+    return with_mode(mode, n_sites, [&](auto l, auto m) {
+        using L = decltype(l);
+        return with_vb<T>(a.vb, [&](auto vb) {
+            return launch_lanczos_one<L, decltype(m)::value, T, decltype(vb)::value>(B, a, lds, st);
+        });
+    });
 }
 
 }  // namespace ftlm

@@ -10,6 +10,9 @@ namespace ftlm {
 
 constexpr int kBlock = 256;      // threads per workgroup: four wave64s
 constexpr int kWaves = kBlock / 64;
+constexpr int kMaxSteps = 4096;  // row stride of the device alpha/beta arrays
+constexpr int kMaxChains = 64;
+constexpr int kMaxPlanSectors = 65;
 
 // Per-chain Lanczos state, one per vector column, in device memory. The
 // stored vector of step k is u_k with q_k = s_cur * u_k (the normalization
@@ -55,12 +58,8 @@ struct SectorDev {
 
 enum Epilogue { kEpiPlain = 0, kEpiLanczos = 1 };
 
-// One multi-vector H.x launch over rows [row0, row0 + nrows) and the
+// One plain multi-vector H.x launch over rows [row0, row0 + nrows) and the
 // columns [col0, col0 + vb) of [D][ld] blocks x (input) and y (output).
-// In the Lanczos epilogue, y holds u_{k-1} on entry and receives
-// w = s_k (H u_k) - beta_{k-1} s_{k-1} u_{k-1}; each workgroup writes its FP64
-// partial of <u_k, w> per column to partials[block * pstride + col], and the
-// last workgroup to finish sums them in block order into chains[col].alpha.
 struct HvLaunch {
     const void* x;
     void* y;
@@ -70,16 +69,50 @@ struct HvLaunch {
     uint32_t nrows;
     int vb;
     int dtype;
-    int epi;
-    int first;          // Lanczos step 1: no previous vector
-    int pstride;
     int grid;
-    Chain* chains;
-    double* partials;
+};
+
+// One sector of a Lanczos launch (one sector or all sectors of a plan), in
+// device memory. Its blocks are [block0, block0 + G) of the launch grid, with
+// G = rows_grid(D) so the reduction order of every column depends on D only.
+struct SecWork {
+    SectorDev S;
+    void* u[2];          // [D][ld] vector blocks; step k reads u_k from u[(k-1)&1]
+    Chain* chains;       // [ld]
+    double* partials;    // [G][ld]
     uint32_t* ticket;
+    double* alpha;       // [ld][kMaxSteps]
+    double* beta;        // [ld][kMaxSteps]
+    const uint64_t* keys;  // [ld] start-vector stream keys
+    uint64_t r0;         // sample index of column 0
+    uint32_t G;
+    uint32_t block0;
+    int32_t m_eff;       // min(M, D)
+    int32_t pad;
+};
+
+// Kernel arguments of the Lanczos kernels over a list of sectors. Columns
+// [col0, col0 + vb) of every sector's [D][ld] blocks.
+struct LanczosLaunch {
+    const SecWork* secs;
+    int nsec;
+    int grid;            // total blocks (sum of the sectors' G, 8-aligned)
+    uint64_t ld;
+    uint32_t col0;
+    int vb;
+    int dtype;
+    int step;            // k, 1-based
+    double eps;          // stopping threshold
+    int dist;            // start-vector distribution
+    int mode;            // index mode shared by the sectors (host dispatch)
+    int n_sites;         // N shared by the sectors (host dispatch)
 };
 
 hipError_t launch_hv(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st);
+hipError_t launch_hv_lanczos(const BondTable& B, const LanczosLaunch& a, size_t lds, hipStream_t st);
+hipError_t launch_start(const LanczosLaunch& a, hipStream_t st);
+hipError_t launch_update(const LanczosLaunch& a, hipStream_t st);
+hipError_t launch_chain_init(const LanczosLaunch& a, hipStream_t st);
 
 // Sector table builders and index kernels (sector.hip).
 hipError_t launch_build_basis(const SectorDev& s, hipStream_t st);
@@ -91,55 +124,43 @@ hipError_t launch_unrank(const SectorDev& s, const uint64_t* idx, uint64_t* labe
 hipError_t launch_neighbors(const SectorDev& s, const BondTable& B, uint64_t t0, uint64_t count,
                             uint64_t* out, hipStream_t st);
 
-// Lanczos helpers (lanczos.hip).
-struct StartLaunch {
-    void* q;              // [D][ld] block, columns [col0, col0 + ncols)
-    uint64_t ld;
-    uint32_t col0;
-    int ncols;
-    int dtype;
-    int dist;
-    uint64_t keys[64];    // SplitMix64 stream key per column
-    uint64_t sample[64];  // global sample index per column (FTLM_UNIT)
-    int grid;
-    int pstride;
-    Chain* chains;
-    double* partials;
-    uint32_t* ticket;
-};
-hipError_t launch_start(const SectorDev& s, const StartLaunch& a, hipStream_t st);
-
-struct UpdateLaunch {
-    void* u;            // u_k, [D][ld]
-    void* w;            // w in, u_{k+1} out, [D][ld]
-    uint64_t ld;
-    uint32_t col0;
-    int ncols;
-    int dtype;
-    int grid;
-    int pstride;
-    int step;           // k (1-based)
-    int m_eff;          // min(M, D)
-    double eps;
-    int M;              // row stride of the alpha/beta arrays
-    Chain* chains;
-    double* partials;
-    uint32_t* ticket;
-    double* alpha;      // [R][M]
-    double* beta;       // [R][M]
-};
-hipError_t launch_update(const SectorDev& s, const UpdateLaunch& a, hipStream_t st);
-hipError_t launch_chain_init(Chain* chains, int n, uint32_t* tickets, int nt, hipStream_t st);
+// LDS bytes of the H.x kernels: FP64 scratch, then (CR) the binomial table
+// and one [site][lane] slab of Y values per wave.
+__host__ __device__ constexpr size_t hv_red_bytes() { return kBlock * sizeof(double); }
+inline size_t hv_binom_lds_bytes(int n_sites, int bw, int mode) {
+    return mode == kModeCr ? ((size_t(n_sites) * size_t(bw) * 4 + 15) & ~size_t(15)) : 0;
+}
+inline size_t hv_slab_lds_bytes(int n_sites, int mode) {
+    return mode == kModeCr ? size_t(kWaves) * size_t(n_sites) * 64 * 4 : 0;
+}
+inline size_t hv_lds_bytes(const SectorDev& s) {
+    return hv_red_bytes() + hv_binom_lds_bytes(s.n_sites, s.bw, s.mode) + hv_slab_lds_bytes(s.n_sites, s.mode);
+}
 
 // Grid of the persistent row kernels for a row count: a multiple of 8 (one
 // share per XCD) capped near the number of resident workgroups, so reduction
 // partials depend on the row count only.
-inline int rows_grid(uint32_t nrows) {
+__host__ __device__ inline uint32_t rows_grid(uint32_t nrows) {
     const uint32_t tiles = (nrows + kBlock - 1) / kBlock;
-    if (tiles < 8) return int(tiles == 0 ? 1 : tiles);
+    if (tiles < 8) return tiles == 0 ? 1u : tiles;
     const uint32_t cap = 2048;
-    uint32_t g = tiles < cap ? tiles : cap;
-    return int((g + 7) & ~7u);
+    const uint32_t g = tiles < cap ? tiles : cap;
+    return (g + 7) & ~7u;
+}
+
+// The sector owning block `b` of a multi-sector launch, by a wave-uniform
+// scan of the block ranges; *local receives the block's index inside the
+// sector, or the function returns -1 for a padding block.
+__device__ __forceinline__ int sector_of_block(const SecWork* secs, int nsec, uint32_t b,
+                                               uint32_t* local) {
+    for (int s = 0; s < nsec; ++s) {
+        const uint32_t b0 = secs[s].block0, G = secs[s].G;
+        if (b >= b0 && b < b0 + G) {
+            *local = b - b0;
+            return s;
+        }
+    }
+    return -1;
 }
 
 }  // namespace ftlm

@@ -1,12 +1,21 @@
-// Lanczos kernels: start vectors and the second half of a Lanczos step
-// (paper Sec. 2, the recursion after Eq. 3, without reorthogonalization).
-// The first half of a step (w = H q_k - beta_{k-1} q_{k-1} and alpha_k) is the
-// Lanczos epilogue of the H.x kernel.
+// Lanczos kernels over a list of sectors: start vectors and the second half
+// of a Lanczos step (paper Sec. 2, the recursion after Eq. 3, without
+// reorthogonalization). The first half of a step (w = H q_k - beta_{k-1}
+// q_{k-1} and alpha_k) is hv_lanczos_kernel. A launch covers one sector or
+// every sector of a plan; each sector owns a contiguous range of blocks.
 #include <math.h>
 
 #include "hv_impl.hpp"
 
 namespace ftlm {
+
+template <typename T>
+hipError_t launch_lanczos_typed(int, int, const BondTable&, const LanczosLaunch&, size_t, hipStream_t);
+
+hipError_t launch_hv_lanczos(const BondTable& B, const LanczosLaunch& a, size_t lds, hipStream_t st) {
+    return a.dtype == 0 ? launch_lanczos_typed<float>(a.mode, a.n_sites, B, a, lds, st)
+                        : launch_lanczos_typed<double>(a.mode, a.n_sites, B, a, lds, st);
+}
 
 namespace {
 
@@ -34,39 +43,45 @@ __device__ __forceinline__ double start_entry(int dist, uint64_t key, uint64_t i
     return i == sample ? 1.0 : 0.0;
 }
 
-// Writes up to four columns of start vectors and their FP64 norms; the last
-// workgroup turns the norms into each chain's initial scale s_1 = 1 / |u_1|.
+// Writes columns [col0, col0 + vb) (vb <= CB) of every sector's start block
+// u_1 and their FP64 norms; the last block of a sector turns the norms into
+// each chain's initial scale s_1 = 1 / |u_1|.
 template <typename T, int CB>
-__global__ __launch_bounds__(kBlock) void start_kernel(SectorDev S, StartLaunch a, int cbase) {
+__global__ __launch_bounds__(kBlock) void start_kernel(LanczosLaunch a) {
     __shared__ double red[kBlock];
     __shared__ int flag;
-    T* q = static_cast<T*>(a.q);
-    const int nc = min(CB, a.ncols - cbase);
+    uint32_t local = 0;
+    const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
+    if (s < 0) return;
+    const SecWork& sw = a.secs[s];
+    const uint32_t dim = sw.S.dim;
+    T* q = static_cast<T*>(sw.u[0]);
+    const int nc = a.vb < CB ? a.vb : CB;
     double part[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) part[c] = 0.0;
-    const uint32_t ntiles = (S.dim + kBlock - 1) / kBlock;
-    for_each_tile(ntiles, [&](uint32_t tile) {
+    const uint32_t ntiles = (dim + kBlock - 1) / kBlock;
+    for_each_tile(ntiles, local, sw.G, [&](uint32_t tile) {
         const uint32_t t = tile * kBlock + threadIdx.x;
-        if (t >= S.dim) return;
+        if (t >= dim) return;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             if (c < nc) {
-                const T v = T(start_entry(a.dist, a.keys[cbase + c], t, a.sample[cbase + c]));
-                q[uint64_t(t) * a.ld + a.col0 + cbase + c] = v;
+                const uint32_t col = a.col0 + c;
+                const T v = T(start_entry(a.dist, sw.keys[col], t, sw.r0 + col));
+                q[uint64_t(t) * a.ld + col] = v;
                 part[c] += double(v) * double(v);
             }
         }
     });
     block_sum<CB>(part, red);
-    if (threadIdx.x < nc)
-        a.partials[size_t(blockIdx.x) * a.pstride + a.col0 + cbase + threadIdx.x] = red[kWaves * CB + threadIdx.x];
-    if (last_block(a.ticket, &flag)) {
+    if (threadIdx.x < nc) sw.partials[size_t(local) * a.ld + a.col0 + threadIdx.x] = red[kWaves * CB + threadIdx.x];
+    if (last_block(sw.ticket, sw.G, &flag)) {
         for (int c = 0; c < nc; ++c) {
-            const int col = int(a.col0) + cbase + c;
-            const double tot = grid_sum_col(a.partials, int(gridDim.x), a.pstride, col, red);
+            const int col = int(a.col0) + c;
+            const double tot = grid_sum_col(sw.partials, int(sw.G), int(a.ld), col, red);
             if (threadIdx.x == 0) {
-                Chain* ch = &a.chains[col];
+                Chain* ch = &sw.chains[col];
                 const double nrm = sqrt(tot);
                 ch->norm = nrm;
                 ch->s_cur = nrm > 0.0 ? 1.0 / nrm : 0.0;
@@ -79,31 +94,36 @@ __global__ __launch_bounds__(kBlock) void start_kernel(SectorDev S, StartLaunch 
                 chain_set_hv(ch);
             }
         }
-        if (threadIdx.x == 0) *a.ticket = 0u;
+        if (threadIdx.x == 0) *sw.ticket = 0u;
     }
 }
 
-// Second half of Lanczos step k for a block of VB chains:
-//   w -= alpha_k q_k  (q_k = s_k u_k),  beta_k = |w|,  u_{k+1} = w,
-// with |w|^2 accumulated in FP64 per workgroup and summed in fixed order by
-// the last workgroup, which then records alpha_k and beta_k and applies the
-// stopping rule: the chain stops after step k when k reaches min(M, D) or
+// Second half of Lanczos step k for columns [col0, col0 + VB) of every
+// sector:  w -= alpha_k q_k (q_k = s_k u_k),  beta_k = |w|,  u_{k+1} = w,
+// with |w|^2 accumulated in FP64 per block and summed in fixed order by the
+// sector's last block, which then records alpha_k and beta_k and applies the
+// stopping rule: a chain stops after step k when k reaches min(M, D) or
 // beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}). A stopped chain gets
 // zero scales, so its columns stay zero in every later step.
 template <typename T, int VB>
-__global__ __launch_bounds__(kBlock) void update_kernel(SectorDev S, UpdateLaunch a) {
+__global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
     __shared__ double red[kBlock];
     __shared__ int flag;
-    const T* __restrict__ u = static_cast<const T*>(a.u);
-    T* __restrict__ w = static_cast<T*>(a.w);
-    const Chain* chains = a.chains + a.col0;
+    uint32_t local = 0;
+    const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
+    if (s < 0) return;
+    const SecWork& sw = a.secs[s];
+    const uint32_t dim = sw.S.dim;
+    const T* __restrict__ u = static_cast<const T*>(sw.u[(a.step - 1) & 1]);
+    T* __restrict__ w = static_cast<T*>(sw.u[a.step & 1]);
+    const Chain* chains = sw.chains + a.col0;
     double part[VB];
 #pragma unroll
     for (int c = 0; c < VB; ++c) part[c] = 0.0;
-    const uint32_t ntiles = (S.dim + kBlock - 1) / kBlock;
-    for_each_tile(ntiles, [&](uint32_t tile) {
+    const uint32_t ntiles = (dim + kBlock - 1) / kBlock;
+    for_each_tile(ntiles, local, sw.G, [&](uint32_t tile) {
         const uint32_t t = tile * kBlock + threadIdx.x;
-        if (t >= S.dim) return;
+        if (t >= dim) return;
         T uu[VB], ww[VB];
         load_row<T, VB>(u + uint64_t(t) * a.ld + a.col0, uu);
         T* wrow = w + uint64_t(t) * a.ld + a.col0;
@@ -117,23 +137,22 @@ __global__ __launch_bounds__(kBlock) void update_kernel(SectorDev S, UpdateLaunc
         store_row<T, VB>(wrow, ww);
     });
     block_sum<VB>(part, red);
-    if (threadIdx.x < VB)
-        a.partials[size_t(blockIdx.x) * a.pstride + a.col0 + threadIdx.x] = red[kWaves * VB + threadIdx.x];
-    if (last_block(a.ticket, &flag)) {
+    if (threadIdx.x < VB) sw.partials[size_t(local) * a.ld + a.col0 + threadIdx.x] = red[kWaves * VB + threadIdx.x];
+    if (last_block(sw.ticket, sw.G, &flag)) {
         for (int c = 0; c < VB; ++c) {
             const int col = int(a.col0) + c;
-            const double tot = grid_sum_col(a.partials, int(gridDim.x), a.pstride, col, red);
+            const double tot = grid_sum_col(sw.partials, int(sw.G), int(a.ld), col, red);
             if (threadIdx.x == 0) {
-                Chain* ch = &a.chains[col];
+                Chain* ch = &sw.chains[col];
                 if (ch->active) {
                     const double bk = sqrt(tot);
                     const double ak = ch->alpha;
-                    a.alpha[size_t(col) * a.M + (a.step - 1)] = ak;
-                    a.beta[size_t(col) * a.M + (a.step - 1)] = bk;
+                    sw.alpha[size_t(col) * kMaxSteps + (a.step - 1)] = ak;
+                    sw.beta[size_t(col) * kMaxSteps + (a.step - 1)] = bk;
                     const double amax = fmax(ch->amax, fmax(fabs(ak), ch->beta_prev));
                     ch->amax = amax;
                     ch->steps = a.step;
-                    if (a.step >= a.m_eff || bk <= a.eps * amax) {
+                    if (a.step >= sw.m_eff || bk <= a.eps * amax) {
                         ch->active = 0;
                         ch->s_cur = 0.0;
                         ch->s_prev = 0.0;
@@ -147,57 +166,45 @@ __global__ __launch_bounds__(kBlock) void update_kernel(SectorDev S, UpdateLaunc
                 }
             }
         }
-        if (threadIdx.x == 0) *a.ticket = 0u;
+        if (threadIdx.x == 0) *sw.ticket = 0u;
     }
 }
 
-__global__ void chain_init_kernel(Chain* chains, int n, uint32_t* tickets, int nt) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+// Zeroes every sector's chain states and ticket (one block per sector).
+__global__ void chain_init_kernel(LanczosLaunch a) {
+    if (int(blockIdx.x) >= a.nsec) return;
+    const SecWork& sw = a.secs[blockIdx.x];
+    for (int i = threadIdx.x; i < int(a.ld); i += blockDim.x) {
         Chain c{};
-        chains[i] = c;
+        sw.chains[i] = c;
     }
-    for (int i = threadIdx.x; i < nt; i += blockDim.x) tickets[i] = 0u;
-}
-
-template <typename T>
-hipError_t launch_update_t(const SectorDev& s, const UpdateLaunch& a, hipStream_t st) {
-    const dim3 g(unsigned(a.grid)), b(kBlock);
-    switch (a.ncols) {
-        case 1: hipLaunchKernelGGL((update_kernel<T, 1>), g, b, 0, st, s, a); break;
-        case 2: hipLaunchKernelGGL((update_kernel<T, 2>), g, b, 0, st, s, a); break;
-        case 4: hipLaunchKernelGGL((update_kernel<T, 4>), g, b, 0, st, s, a); break;
-        case 8: hipLaunchKernelGGL((update_kernel<T, 8>), g, b, 0, st, s, a); break;
-        case 16: hipLaunchKernelGGL((update_kernel<T, 16>), g, b, 0, st, s, a); break;
-        case 20:
-            if constexpr (sizeof(T) == 4) { hipLaunchKernelGGL((update_kernel<T, 20>), g, b, 0, st, s, a); break; }
-            else return hipErrorInvalidValue;
-        case 32:
-            if constexpr (sizeof(T) == 4) { hipLaunchKernelGGL((update_kernel<T, 32>), g, b, 0, st, s, a); break; }
-            else return hipErrorInvalidValue;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (threadIdx.x == 0) *sw.ticket = 0u;
 }
 
 }  // namespace
 
-hipError_t launch_start(const SectorDev& s, const StartLaunch& a, hipStream_t st) {
+hipError_t launch_start(const LanczosLaunch& a, hipStream_t st) {
     const dim3 g(unsigned(a.grid)), b(kBlock);
-    for (int cb = 0; cb < a.ncols; cb += 4) {
-        if (a.dtype == 0) hipLaunchKernelGGL((start_kernel<float, 4>), g, b, 0, st, s, a, cb);
-        else hipLaunchKernelGGL((start_kernel<double, 4>), g, b, 0, st, s, a, cb);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if (a.vb < 1 || a.vb > 4) return hipErrorInvalidValue;
+    if (a.dtype == 0) hipLaunchKernelGGL((start_kernel<float, 4>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((start_kernel<double, 4>), g, b, 0, st, a);
+    return hipGetLastError();
 }
 
-hipError_t launch_update(const SectorDev& s, const UpdateLaunch& a, hipStream_t st) {
-    return a.dtype == 0 ? launch_update_t<float>(s, a, st) : launch_update_t<double>(s, a, st);
+hipError_t launch_update(const LanczosLaunch& a, hipStream_t st) {
+    const dim3 g(unsigned(a.grid)), b(kBlock);
+    auto go = [&](auto tt) {
+        using T = decltype(tt);
+        return with_vb<T>(a.vb, [&](auto vb) {
+            hipLaunchKernelGGL((update_kernel<T, decltype(vb)::value>), g, b, 0, st, a);
+            return hipGetLastError();
+        });
+    };
+    return a.dtype == 0 ? go(float{}) : go(double{});
 }
 
-hipError_t launch_chain_init(Chain* chains, int n, uint32_t* tickets, int nt, hipStream_t st) {
-    hipLaunchKernelGGL(chain_init_kernel, dim3(1), dim3(256), 0, st, chains, n, tickets, nt);
+hipError_t launch_chain_init(const LanczosLaunch& a, hipStream_t st) {
+    hipLaunchKernelGGL(chain_init_kernel, dim3(unsigned(a.nsec)), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

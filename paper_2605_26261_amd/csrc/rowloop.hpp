@@ -6,21 +6,21 @@
 
 namespace ftlm {
 
-// Calls f(tile) for the tiles of kBlock rows this workgroup owns. With a grid
-// that is a multiple of 8, workgroup i runs on XCD i mod 8 (round-robin
-// dispatch), so XCD x gets the x-th contiguous eighth of the tiles and its
-// L2 sees neighbouring rows; inside a share the XCD's workgroups stride.
+// Calls f(tile) for the tiles of kBlock rows owned by block `bid` of a
+// (sub-)grid of G blocks. With G a multiple of 8 and the sub-grid starting
+// at a multiple of 8, block i runs on XCD i mod 8 (round-robin dispatch), so
+// XCD x gets the x-th contiguous eighth of the tiles and its L2 sees
+// neighbouring rows; inside a share the XCD's blocks stride.
 template <typename F>
-__device__ __forceinline__ void for_each_tile(uint32_t ntiles, F&& f) {
-    const uint32_t G = gridDim.x;
+__device__ __forceinline__ void for_each_tile(uint32_t ntiles, uint32_t bid, uint32_t G, F&& f) {
     if (G >= 8 && (G & 7u) == 0) {
-        const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3, per = G >> 3;
+        const uint32_t xcd = bid & 7u, slot = bid >> 3, per = G >> 3;
         const uint32_t chunk = (ntiles + 7u) >> 3;
         const uint32_t begin = xcd * chunk;
         const uint32_t end = begin + chunk < ntiles ? begin + chunk : ntiles;
         for (uint32_t tile = begin + slot; tile < end; tile += per) f(tile);
     } else {
-        for (uint32_t tile = blockIdx.x; tile < ntiles; tile += G) f(tile);
+        for (uint32_t tile = bid; tile < ntiles; tile += G) f(tile);
     }
 }
 
@@ -47,15 +47,15 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
     __syncthreads();
 }
 
-// Publishes this block's partials and reports whether it is the last block
-// of the grid to do so (then every partial is visible to it). The ticket is
-// reset by that last block for the next launch on the stream.
-__device__ __forceinline__ bool last_block(uint32_t* ticket, int* flag_lds) {
+// Publishes this block's partials and reports whether it is the last of the
+// G blocks sharing `ticket` to do so (then every partial is visible to it).
+// The ticket is reset by that last block for the next launch on the stream.
+__device__ __forceinline__ bool last_block(uint32_t* ticket, uint32_t G, int* flag_lds) {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t prev = atomicAdd(ticket, 1u);
-        *flag_lds = (prev == gridDim.x - 1) ? 1 : 0;
+        *flag_lds = (prev == G - 1) ? 1 : 0;
     }
     __syncthreads();
     const bool last = *flag_lds != 0;

@@ -18,9 +18,9 @@ def log_temperatures(n=200, t_min=0.05, t_max=10.0):
     return t_min * (t_max / t_min) ** (k / (n - 1))
 
 
-def sector_samples(sector, graph, R, M, seed, dist, dtype, r0=0, work=None, stream=None):
-    """Runs R chains in one batch; returns the thermo record of the sector."""
-    alpha, beta, steps = ftlm.lanczos(sector, graph, seed, r0, R, M, dist, dtype, work=work, stream=stream)
+def records_from_coefficients(n_sites, n_up, dim, alpha, beta, steps):
+    """Host Ritz solves of R chains -> a thermo record of the sector."""
+    R, M = alpha.shape
     theta = np.zeros((R, M))
     weight = np.zeros((R, M))
     for r in range(R):
@@ -28,8 +28,14 @@ def sector_samples(sector, graph, R, M, seed, dist, dtype, r0=0, work=None, stre
         th, w = ftlm.ritz(alpha[r, :k], beta[r, :max(k - 1, 1)], k)
         theta[r, :k] = th
         weight[r, :k] = w
-    return {"n_up": sector.n_up, "dim": sector.dim, "mult": multiplicity(sector.n_sites, sector.n_up),
-            "theta": theta, "weight": weight, "steps": steps, "alpha": alpha, "beta": beta}
+    return {"n_up": n_up, "dim": dim, "mult": multiplicity(n_sites, n_up), "theta": theta, "weight": weight,
+            "steps": np.asarray(steps), "alpha": alpha, "beta": beta}
+
+
+def sector_samples(sector, graph, R, M, seed, dist, dtype, r0=0, work=None, stream=None):
+    """Runs R chains in one batch; returns the thermo record of the sector."""
+    alpha, beta, steps = ftlm.lanczos(sector, graph, seed, r0, R, M, dist, dtype, work=work, stream=stream)
+    return records_from_coefficients(sector.n_sites, sector.n_up, sector.dim, alpha, beta, steps)
 
 
 def run(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, temps=None, g=1.0,
@@ -49,4 +55,22 @@ def run(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, t
         for k in ("theta", "weight", "steps", "alpha", "beta"):
             rec[k] = np.concatenate([p[k] for p in parts])
         recs.append(rec)
+    return ftlm.thermo(n_sites, recs, temps, g), recs
+
+
+def plan_records(plan, n_sites, seed, dist, r0=0, use_graph=True):
+    """One run of an all-sector plan -> per-sector thermo records."""
+    import math
+    alpha, beta, steps = plan.run(seed, dist, r0=r0, use_graph=use_graph)
+    return [records_from_coefficients(n_sites, nu, math.comb(n_sites, nu), alpha[i], beta[i], steps[i])
+            for i, nu in enumerate(plan.n_ups)]
+
+
+def run_plan(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, temps=None, g=1.0,
+             use_graph=True, device="cuda"):
+    """Full FTLM over the listed sectors as one batched plan."""
+    temps = log_temperatures() if temps is None else temps
+    graph = ftlm.Graph(n_sites, bonds)
+    plan = ftlm.Plan(graph, n_ups, mode, R, M, dtype, device=device)
+    recs = plan_records(plan, n_sites, seed, dist, use_graph=use_graph)
     return ftlm.thermo(n_sites, recs, temps, g), recs

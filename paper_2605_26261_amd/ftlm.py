@@ -65,6 +65,10 @@ _sig("ftlm_hv_rows", _i32, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _u64, _vp])
 _sig("ftlm_start_vectors", _i32, [_vp, _u64, _u64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _sig("ftlm_lanczos_workspace_bytes", _i32, [_vp, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("ftlm_lanczos", _i32, [_vp, _vp, _u64, _u64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _vp])
+_sig("ftlm_plan_workspace_bytes", _i32, [_vp, _i32, _vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
+_sig("ftlm_plan_create", _i32, [_vp, _i32, _vp, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)])
+_sig("ftlm_plan_run", _i32, [_vp, _u64, _u64, _i32, _i32, _vp, _vp, _vp, _vp])
+_sig("ftlm_plan_destroy", None, [_vp])
 _sig("ftlm_ritz", _i32, [_i32, _vp, _vp, _vp, _vp])
 _sig("ftlm_thermo", _i32, [_i32, _i32, ctypes.POINTER(SectorResult), _i32, _vp, _dbl, _vp, _vp, _vp, _vp])
 _sig("ftlm_stats_enable", _i32, [_i32])
@@ -225,6 +229,43 @@ def lanczos(sector, graph, seed, r0, R, M, dist, dtype, work=None, stream=None):
     _check(_lib.ftlm_lanczos(sector.handle, graph.handle, seed, r0, R, M, dist, dtype, _dptr(work), work.numel(),
                              _hptr(alpha), _hptr(beta), _hptr(steps), _stream(stream)))
     return alpha, beta, steps
+
+
+def plan_workspace_bytes(graph, n_ups, mode, R, dtype):
+    nu = np.ascontiguousarray(n_ups, dtype=np.int32)
+    n = _sz()
+    _check(_lib.ftlm_plan_workspace_bytes(graph.handle, len(nu), _hptr(nu), mode, R, dtype, ctypes.byref(n)))
+    return n.value
+
+
+class Plan:
+    """ftlm_plan: R chains in each listed sector, one launch per kernel per
+    Lanczos step over all sectors; owns its device arena."""
+
+    def __init__(self, graph, n_ups, mode, R, M, dtype, device="cuda", stream=None):
+        self.n_ups = [int(v) for v in n_ups]
+        nu = np.ascontiguousarray(self.n_ups, dtype=np.int32)
+        self.arena = _empty_device(plan_workspace_bytes(graph, nu, mode, R, dtype), device)
+        h = _vp()
+        _check(_lib.ftlm_plan_create(graph.handle, len(nu), _hptr(nu), mode, R, M, dtype, _dptr(self.arena),
+                                     self.arena.numel(), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.R, self.M = R, M
+
+    def run(self, seed, dist, r0=0, use_graph=True, stream=None):
+        """Returns alpha, beta [S, R, M] and steps [S, R]."""
+        S = len(self.n_ups)
+        alpha = np.zeros((S, self.R, self.M))
+        beta = np.zeros((S, self.R, self.M))
+        steps = np.zeros((S, self.R), dtype=np.int32)
+        _check(_lib.ftlm_plan_run(self.handle, seed, r0, dist, 1 if use_graph else 0, _hptr(alpha), _hptr(beta),
+                                  _hptr(steps), _stream(stream)))
+        return alpha, beta, steps
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.ftlm_plan_destroy(self.handle)
+            self.handle = None
 
 
 def ritz(alpha, beta, m=None):
