@@ -198,6 +198,29 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
                  int M, int dist, int dtype, void* work_dev, size_t work_bytes, double* alpha_host,
                  double* beta_host, int32_t* steps_host, void* stream);
 
+/* ---- autotuning of the batch width -------------------------------------------
+ * The B chains of a Lanczos batch share each row's index work (Sec. 2,
+ * batched Lanczos; the paper picks B adaptively, Sec. 3.4). ftlm_autotune
+ * times the multi-vector H.x of the sector at candidate batch widths
+ * B in {1, 2, 4, 8, 16, 20, 32} (B <= R) with HIP events on `stream`, using
+ * work_dev (at least ftlm_lanczos_workspace_bytes(s, R, dtype) bytes) as
+ * scratch, and returns the B that minimizes the time of one Lanczos step of
+ * all R chains run in ceil(R / B) batches. Results are cached per (N, n_up,
+ * bonds, mode, dtype, R) for the life of the process; the file named by the
+ * environment variable FTLM_AUTOTUNE_CACHE, when set, is read and appended
+ * (one "key batch ms" line per entry). The workgroup grid is not tuned: it
+ * fixes the FP64 reduction order, so results never depend on the choice. */
+typedef struct ftlm_tuning {
+    int32_t batch;          /* chains per ftlm_lanczos call */
+    int32_t n_candidates;
+    int32_t widths[8];      /* candidate B */
+    double ms[8];           /* measured H.x milliseconds at each B */
+    double ms_per_step;     /* predicted step time of all R chains at `batch` */
+    int32_t cached;         /* 1 when served from the cache */
+} ftlm_tuning;
+int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, void* work_dev,
+                  size_t work_bytes, void* stream, ftlm_tuning* out);
+
 /* ---- batched all-sector plans ---------------------------------------------
  * A plan runs R Lanczos chains in each of several S^z sectors of one graph
  * (for example every sector M >= 0) with one launch per kernel per Lanczos

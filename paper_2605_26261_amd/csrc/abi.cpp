@@ -7,326 +7,16 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
-#include "ftlm.h"
-#include "host_math.hpp"
-#include "kernels.hpp"
+#include "host.hpp"
 
 using namespace ftlm;
-
-struct ftlm_graph {
-    int n_sites = 0;
-    std::vector<int> bi, bj;   // merged bonds, caller order of first appearance
-    std::vector<double> J;
-    int n_input = 0;               // bonds as given (before merging)
-    std::vector<int> merged_of_input;
-    BondTable table{};
-};
-
-struct ftlm_sector {
-    int n_sites = 0, n_up = 0, mode = 0;
-    uint64_t dim = 0;
-    void* table = nullptr;
-    size_t bytes = 0;
-    TableLayout layout{};
-    std::vector<uint32_t> binom_host;
-    SectorDev dev{};
-};
-
-namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
-int ok() {
-    g_err.clear();
-    return FTLM_OK;
-}
-
-#define HIP_CHECK(expr)                                                                   \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess) return fail(FTLM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-uint64_t binom_u64(int n, int k) {
-    if (n < 0 || k < 0 || k > n) return 0;
-    if (k > n - k) k = n - k;
-    unsigned __int128 c = 1;
-    for (int i = 1; i <= k; ++i) c = c * unsigned(n - k + i) / unsigned(i);
-    return uint64_t(c);
-}
-
-// ---- start-vector keys: SplitMix64 (Steele, Lea, Flood 2014) --------------
-constexpr uint64_t kGammaHost = 0x9e3779b97f4a7c15ull;
-uint64_t mix64_host(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-uint64_t first_output(uint64_t s) { return mix64_host(s + kGammaHost); }
-// Key of sample r in the sector with n_up up spins.
-uint64_t stream_key(uint64_t seed, int n_up, uint64_t r) {
-    uint64_t k = first_output(seed);
-    k = first_output(k ^ uint64_t(uint32_t(n_up)));
-    return first_output(k ^ r);
-}
-
-// ---- stats -------------------------------------------------------------------
-struct Stats {
-    std::mutex mu;
-    bool on = false;
-    int64_t launches = 0;
-    double ms = 0.0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-} g_stats;
-
-struct HvTimer {
-    hipEvent_t a = nullptr, b = nullptr;
-    hipStream_t st;
-    explicit HvTimer(hipStream_t s) : st(s) {
-        std::lock_guard<std::mutex> lk(g_stats.mu);
-        if (!g_stats.on) return;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
-        (void)hipEventRecord(a, st);
-    }
-    ~HvTimer() {
-        if (!a) return;
-        (void)hipEventRecord(b, st);
-        std::lock_guard<std::mutex> lk(g_stats.mu);
-        g_stats.pending.emplace_back(a, b);
-    }
-};
-
-// ---- column chunking of a [D][ld] block --------------------------------------
-// Splits columns [0, nvec) into kernel widths, widest first, keeping every
-// vector access naturally aligned (ld, col0 and the base pointers).
-std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtype, const std::vector<const void*>& ptrs) {
-    const size_t es = dtype == FTLM_F32 ? 4 : 8;
-    static const int w32[] = {32, 20, 16, 8, 4, 2, 1};
-    static const int w64[] = {16, 8, 4, 2, 1};
-    const int* widths = dtype == FTLM_F32 ? w32 : w64;
-    const int nw = dtype == FTLM_F32 ? 7 : 5;
-    std::vector<std::pair<int, int>> out;
-    int col = 0;
-    while (col < nvec) {
-        for (int i = 0; i < nw; ++i) {
-            const int vb = widths[i];
-            if (vb > nvec - col) continue;
-            size_t vbytes = es;
-            if (es == 4 && vb % 4 == 0) vbytes = 16;
-            else if (vb % 2 == 0) vbytes = 2 * es;
-            bool aligned = (ld * es) % vbytes == 0 && (size_t(col) * es) % vbytes == 0;
-            for (const void* p : ptrs) aligned = aligned && (reinterpret_cast<uintptr_t>(p) % vbytes == 0);
-            if (!aligned) continue;
-            out.emplace_back(col, vb);
-            col += vb;
-            break;
-        }
-    }
-    return out;
-}
-
-std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype,
-                                               std::initializer_list<const void*> ptrs) {
-    return column_chunks_v(nvec, ld, dtype, std::vector<const void*>(ptrs));
-}
-
-int check_dtype(int dtype) {
-    if (dtype != FTLM_F32 && dtype != FTLM_F64) return fail(FTLM_E_INVALID, "dtype %d is not FTLM_F32/FTLM_F64", dtype);
-    return FTLM_OK;
-}
-
-// ---- Lanczos state layout -----------------------------------------------------
-constexpr int kTicketsPerSector = 1;
-
-// Byte offsets of one sector's Lanczos state inside a workspace or arena.
-struct SectorState {
-    size_t u0, u1, partials, chains, alpha, beta, ticket, keys;
-};
-
-// Lays out the state of a sector of dimension `dim` at `off`; returns the end.
-size_t layout_state(uint64_t dim, int R, int dtype, size_t off, SectorState& st) {
-    const size_t es = dtype == FTLM_F32 ? 4 : 8;
-    st.u0 = off; off = align256(off + size_t(dim) * size_t(R) * es);
-    st.u1 = off; off = align256(off + size_t(dim) * size_t(R) * es);
-    st.partials = off; off = align256(off + size_t(rows_grid(uint32_t(dim))) * size_t(R) * sizeof(double));
-    st.chains = off; off = align256(off + size_t(R) * sizeof(Chain));
-    st.alpha = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
-    st.beta = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
-    st.ticket = off; off = align256(off + kTicketsPerSector * sizeof(uint32_t));
-    st.keys = off; off = align256(off + size_t(R) * sizeof(uint64_t));
-    return off;
-}
-
-template <typename P>
-P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(base) + off); }
-
-// A batch of R chains in each of a list of sectors (one sector for
-// ftlm_lanczos, all sectors of a plan), with the device descriptors of the
-// multi-sector Lanczos kernels. Host copies stay alive until the stream work
-// that reads them has been synchronized.
-struct LanczosJob {
-    int nsec = 0, R = 0, dtype = 0, mode = 0, n_sites = 0, grid = 0;
-    size_t lds = 0;
-    std::vector<SecWork> secs;           // host copies of the descriptors
-    std::vector<uint64_t> keys;          // [nsec][R] stream keys of the run
-    SecWork* dev_secs = nullptr;
-    uint64_t* dev_keys = nullptr;        // first sector's key block; sector s at dev_keys_of[s]
-    std::vector<uint64_t*> key_ptrs;
-    std::vector<std::pair<int, int>> chunks;
-    int max_steps = 0;                   // largest m_eff over the sectors
-
-    LanczosLaunch launch() const {
-        LanczosLaunch a{};
-        a.secs = dev_secs;
-        a.nsec = nsec;
-        a.grid = grid;
-        a.ld = uint64_t(R);
-        a.dtype = dtype;
-        a.eps = dtype == FTLM_F32 ? 1e-6 : 1e-12;
-        a.mode = mode;
-        a.n_sites = n_sites;
-        return a;
-    }
-};
-
-// Fills job.secs for sectors whose tables are described by `devs` and whose
-// state sits at `states` inside `base`; the descriptor array goes to
-// `dev_secs` (device). Blocks: each sector gets rows_grid(D) blocks starting
-// at a multiple of 8.
-void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::vector<SectorState>& states,
-                void* base, int R, int M, int dtype, SecWork* dev_secs) {
-    job.nsec = int(devs.size());
-    job.R = R;
-    job.dtype = dtype;
-    job.mode = devs[0].mode;
-    job.n_sites = devs[0].n_sites;
-    job.dev_secs = dev_secs;
-    job.secs.assign(devs.size(), SecWork{});
-    job.key_ptrs.clear();
-    uint32_t block = 0;
-    size_t lds = 0;
-    job.max_steps = 0;
-    for (size_t i = 0; i < devs.size(); ++i) {
-        SecWork& w = job.secs[i];
-        const SectorState& st = states[i];
-        w.S = devs[i];
-        w.u[0] = at<void>(base, st.u0);
-        w.u[1] = at<void>(base, st.u1);
-        w.chains = at<Chain>(base, st.chains);
-        w.partials = at<double>(base, st.partials);
-        w.ticket = at<uint32_t>(base, st.ticket);
-        w.alpha = at<double>(base, st.alpha);
-        w.beta = at<double>(base, st.beta);
-        w.keys = at<uint64_t>(base, st.keys);
-        job.key_ptrs.push_back(at<uint64_t>(base, st.keys));
-        w.G = rows_grid(devs[i].dim);
-        w.block0 = block;
-        block = (block + w.G + 7) & ~7u;
-        w.m_eff = int(std::min<uint64_t>(uint64_t(M), devs[i].dim));
-        job.max_steps = std::max(job.max_steps, w.m_eff);
-        lds = std::max(lds, hv_lds_bytes(devs[i]));
-    }
-    job.grid = int(block);
-    job.lds = lds;
-    std::vector<const void*> ptrs;
-    for (auto& w : job.secs) {
-        ptrs.push_back(w.u[0]);
-        ptrs.push_back(w.u[1]);
-    }
-    job.chunks = column_chunks_v(R, uint64_t(R), dtype, ptrs);
-}
-
-// Start vectors of samples r0 .. r0 + R - 1 in every sector of the job.
-int job_start(LanczosJob& job, uint64_t seed, uint64_t r0, int dist, hipStream_t st) {
-    job.keys.resize(size_t(job.nsec) * size_t(job.R));
-    for (int s = 0; s < job.nsec; ++s) {
-        job.secs[size_t(s)].r0 = r0;
-        for (int c = 0; c < job.R; ++c)
-            job.keys[size_t(s) * job.R + size_t(c)] = stream_key(seed, job.secs[size_t(s)].S.n_up, r0 + uint64_t(c));
-    }
-    HIP_CHECK(hipMemcpyAsync(job.dev_secs, job.secs.data(), job.secs.size() * sizeof(SecWork),
-                             hipMemcpyHostToDevice, st));
-    for (int s = 0; s < job.nsec; ++s)
-        HIP_CHECK(hipMemcpyAsync(job.key_ptrs[size_t(s)], job.keys.data() + size_t(s) * job.R,
-                                 size_t(job.R) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-    LanczosLaunch a = job.launch();
-    a.dist = dist;
-    HIP_CHECK(launch_chain_init(a, st));
-    for (int c = 0; c < job.R; c += 4) {
-        a.col0 = uint32_t(c);
-        a.vb = std::min(4, job.R - c);
-        HIP_CHECK(launch_start(a, st));
-    }
-    return FTLM_OK;
-}
-
-// Lanczos steps 1..job.max_steps for every chunk of columns.
-int job_steps(const LanczosJob& job, const BondTable& B, hipStream_t st, bool timed = true) {
-    LanczosLaunch a = job.launch();
-    for (int k = 1; k <= job.max_steps; ++k) {
-        a.step = k;
-        for (auto [col, vb] : job.chunks) {
-            a.col0 = uint32_t(col);
-            a.vb = vb;
-            if (timed) {
-                HvTimer timer(st);
-                HIP_CHECK(launch_hv_lanczos(B, a, job.lds, st));
-            } else {
-                HIP_CHECK(launch_hv_lanczos(B, a, job.lds, st));
-            }
-            HIP_CHECK(launch_update(a, st));
-        }
-    }
-    return FTLM_OK;
-}
-
-// Copies sector s's coefficients into [R][M] host arrays (after a sync).
-int job_collect(const LanczosJob& job, int M, double* alpha_host, double* beta_host, int32_t* steps_host,
-                hipStream_t st) {
-    const size_t R = size_t(job.R);
-    std::vector<double> a(size_t(job.nsec) * R * kMaxSteps), b(a.size());
-    std::vector<Chain> ch(size_t(job.nsec) * R);
-    for (int s = 0; s < job.nsec; ++s) {
-        const SecWork& w = job.secs[size_t(s)];
-        HIP_CHECK(hipMemcpyAsync(a.data() + size_t(s) * R * kMaxSteps, w.alpha, R * kMaxSteps * sizeof(double),
-                                 hipMemcpyDeviceToHost, st));
-        HIP_CHECK(hipMemcpyAsync(b.data() + size_t(s) * R * kMaxSteps, w.beta, R * kMaxSteps * sizeof(double),
-                                 hipMemcpyDeviceToHost, st));
-        HIP_CHECK(hipMemcpyAsync(ch.data() + size_t(s) * R, w.chains, R * sizeof(Chain), hipMemcpyDeviceToHost, st));
-    }
-    HIP_CHECK(hipStreamSynchronize(st));
-    for (int s = 0; s < job.nsec; ++s) {
-        for (size_t r = 0; r < R; ++r) {
-            const Chain& c = ch[size_t(s) * R + r];
-            const size_t row = size_t(s) * R + r;
-            steps_host[row] = c.steps;
-            for (int k = 0; k < M; ++k) {
-                const bool in = k < c.steps;
-                alpha_host[row * size_t(M) + size_t(k)] = in ? a[row * kMaxSteps + size_t(k)] : 0.0;
-                beta_host[row * size_t(M) + size_t(k)] = in ? b[row * kMaxSteps + size_t(k)] : 0.0;
-            }
-        }
-    }
-    return FTLM_OK;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -547,11 +237,13 @@ int ftlm_hv(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, void* 
 // ---- start vectors and Lanczos ----------------------------------------------------
 // Single-sector workspace: the sector's Lanczos state followed by its device
 // descriptor.
+}  // extern "C"
+
 namespace {
 
 struct SingleLayout {
     SectorState st;
-    size_t secs, total;
+    size_t secs, bonds, total;
 };
 
 SingleLayout single_layout(uint64_t dim, int R, int dtype) {
@@ -559,6 +251,8 @@ SingleLayout single_layout(uint64_t dim, int R, int dtype) {
     size_t off = layout_state(dim, R, dtype, 0, l.st);
     l.secs = off;
     off = align256(off + sizeof(SecWork));
+    l.bonds = off;
+    off = align256(off + sizeof(BondTable));
     l.total = off;
     return l;
 }
@@ -574,12 +268,15 @@ int check_lanczos_args(const ftlm_sector* s, int R, int dist, int dtype, void* w
     return FTLM_OK;
 }
 
-void single_job(LanczosJob& job, const ftlm_sector* s, int R, int M, int dtype, void* work) {
+void single_job(LanczosJob& job, const ftlm_sector* s, const BondTable& bonds, int R, int M, int dtype, void* work) {
     const SingleLayout l = single_layout(s->dim, R, dtype);
-    job_layout(job, {s->dev}, {l.st}, work, R, M, dtype, at<SecWork>(work, l.secs));
+    job_layout(job, {s->dev}, {l.st}, work, R, M, dtype, at<SecWork>(work, l.secs), {bonds},
+               {at<BondTable>(work, l.bonds)}, {0});
 }
 
 }  // namespace
+
+extern "C" {
 
 int ftlm_lanczos_workspace_bytes(const ftlm_sector* s, int R, int dtype, size_t* bytes) {
     if (!s || !bytes) return fail(FTLM_E_INVALID, "null argument");
@@ -595,7 +292,7 @@ int ftlm_start_vectors(const ftlm_sector* s, uint64_t seed, uint64_t r0, int R, 
     if (!q_dev || !norms_host) return fail(FTLM_E_INVALID, "null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     LanczosJob job;
-    single_job(job, s, R, 1, dtype, work_dev);
+    single_job(job, s, BondTable{}, R, 1, dtype, work_dev);
     job.secs[0].u[0] = q_dev;  // the start block goes to the caller's buffer
     if (int rc = job_start(job, seed, r0, dist, st)) return rc;
     std::vector<Chain> ch(static_cast<size_t>(R));
@@ -614,10 +311,126 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
     if (M < 1 || M > kMaxSteps) return fail(FTLM_E_RANGE, "M %d not in [1, %d]", M, kMaxSteps);
     hipStream_t st = static_cast<hipStream_t>(stream);
     LanczosJob job;
-    single_job(job, s, R, M, dtype, work_dev);
+    single_job(job, s, g->table, R, M, dtype, work_dev);
     if (int rc = job_start(job, seed, r0, dist, st)) return rc;
-    if (int rc = job_steps(job, g->table, st)) return rc;
+    if (int rc = job_steps(job, st)) return rc;
     if (int rc = job_collect(job, M, alpha_host, beta_host, steps_host, st)) return rc;
+    return ok();
+}
+
+// ---- autotuning ----------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct TuneCache {
+    std::mutex mu;
+    bool loaded = false;
+    std::map<std::string, std::pair<int, double>> entries;
+} g_tune;
+
+std::string tune_key(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype) {
+    std::string k = "N" + std::to_string(s->n_sites) + "_u" + std::to_string(s->n_up) + "_m" +
+                    std::to_string(s->mode) + "_t" + std::to_string(dtype) + "_R" + std::to_string(R) + "_b";
+    // the bond structure, so that two graphs with the same size do not share entries
+    uint64_t h = 1469598103934665603ull;
+    for (size_t b = 0; b < g->bi.size(); ++b) {
+        h = (h ^ uint64_t(g->bi[b] * 64 + g->bj[b])) * 1099511628211ull;
+    }
+    return k + std::to_string(h);
+}
+
+void tune_load_file() {
+    if (g_tune.loaded) return;
+    g_tune.loaded = true;
+    const char* path = std::getenv("FTLM_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int batch = 0;
+    double ms = 0;
+    while (std::fscanf(f, "%255s %d %lf", key, &batch, &ms) == 3) g_tune.entries[key] = {batch, ms};
+    std::fclose(f);
+}
+
+void tune_store_file(const std::string& key, int batch, double ms) {
+    const char* path = std::getenv("FTLM_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %.6f\n", key.c_str(), batch, ms);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, void* work_dev, size_t work_bytes,
+                  void* stream, ftlm_tuning* out) {
+    if (!s || !g || !out) return fail(FTLM_E_INVALID, "null argument");
+    if (int rc = check_lanczos_args(s, R, FTLM_PM1, dtype, work_dev, work_bytes)) return rc;
+    if (g->n_sites != s->n_sites) return fail(FTLM_E_INVALID, "graph has %d sites, sector %d", g->n_sites, s->n_sites);
+    std::memset(out, 0, sizeof(*out));
+    const std::string key = tune_key(s, g, R, dtype);
+    {
+        std::lock_guard<std::mutex> lk(g_tune.mu);
+        tune_load_file();
+        auto it = g_tune.entries.find(key);
+        if (it != g_tune.entries.end()) {
+            out->batch = it->second.first;
+            out->ms_per_step = it->second.second;
+            out->cached = 1;
+            return ok();
+        }
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const SingleLayout l = single_layout(s->dim, R, dtype);
+    void* x = at<void>(work_dev, l.st.u0);
+    void* y = at<void>(work_dev, l.st.u1);
+    const int widths[] = {1, 2, 4, 8, 16, 20, 32};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_b = 1;
+    int n = 0;
+    for (int B : widths) {
+        if (B > R || (dtype == FTLM_F64 && B > 16)) continue;
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIP_CHECK(hipEventRecord(e0, st));
+            if (int rc = ftlm_hv(s, g, x, y, B, dtype, stream)) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return rc;
+            }
+            HIP_CHECK(hipEventRecord(e1, st));
+            HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) best_ms = std::min(best_ms, ms);  // the first rep warms up
+        }
+        const double step = double((R + B - 1) / B) * double(best_ms);
+        out->widths[n] = B;
+        out->ms[n] = best_ms;
+        ++n;
+        if (step < best) {
+            best = step;
+            best_b = B;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    out->n_candidates = n;
+    out->batch = best_b;
+    out->ms_per_step = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune.mu);
+        g_tune.entries[key] = {best_b, best};
+        tune_store_file(key, best_b, best);
+    }
     return ok();
 }
 
@@ -647,7 +460,7 @@ namespace {
 // Arena of a plan: the sector descriptors, then per sector its tables and its
 // Lanczos state.
 struct PlanLayout {
-    size_t secs;
+    size_t secs, bonds;
     std::vector<size_t> table;
     std::vector<size_t> table_bytes;
     std::vector<SectorState> state;
@@ -659,6 +472,8 @@ int plan_layout(int n_sites, int n_sectors, const int32_t* n_ups, int mode, int 
     size_t off = 0;
     L.secs = off;
     off = align256(off + size_t(n_sectors) * sizeof(SecWork));
+    L.bonds = off;
+    off = align256(off + sizeof(BondTable));
     for (int i = 0; i < n_sectors; ++i) {
         size_t tb = 0;
         if (int rc = ftlm_sector_table_bytes(n_sites, n_ups[i], mode, &tb)) return rc;
@@ -732,7 +547,8 @@ int ftlm_plan_create(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, i
         p->sectors.push_back(s);
         devs.push_back(s->dev);
     }
-    job_layout(p->job, devs, L.state, arena_dev, R, M, dtype, at<SecWork>(arena_dev, L.secs));
+    job_layout(p->job, devs, L.state, arena_dev, R, M, dtype, at<SecWork>(arena_dev, L.secs), {g->table},
+               {at<BondTable>(arena_dev, L.bonds)}, std::vector<int>(size_t(n_sectors), 0));
     hipError_t e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ready, hipEventDisableTiming);
@@ -755,7 +571,7 @@ int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_gr
     if (use_graph) {
         if (!p->exec) {
             HIP_CHECK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-            const int rc = job_steps(p->job, p->table, p->stream, false);
+            const int rc = job_steps(p->job, p->stream, false);
             hipGraph_t graph = nullptr;
             const hipError_t e = hipStreamEndCapture(p->stream, &graph);
             if (rc != FTLM_OK) {
@@ -768,7 +584,7 @@ int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_gr
         }
         HIP_CHECK(hipGraphLaunch(p->exec, p->stream));
     } else {
-        if (int rc = job_steps(p->job, p->table, p->stream)) return rc;
+        if (int rc = job_steps(p->job, p->stream)) return rc;
     }
     if (int rc = job_collect(p->job, p->M, alpha_host, beta_host, steps_host, p->stream)) return rc;
     return ok();

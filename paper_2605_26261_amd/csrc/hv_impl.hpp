@@ -175,28 +175,32 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, Hv
                                         h.row0, h.nrows, blockIdx.x, gridDim.x, nullptr, false, nullptr);
 }
 
-// First half of Lanczos step k over every sector of the launch (one launch
-// serves one sector or all sectors of a plan): w = H q_k - beta_{k-1} q_{k-1}
+// First half of Lanczos step k over every sector of the launch (one sector,
+// all sectors of a plan, or a server round): w = H q_k - beta_{k-1} q_{k-1}
 // and the FP64 partials of <u_k, w>; the last block of each sector sums the
-// partials in block order into alpha_k (and the update coefficient).
+// partials in block order into alpha_k (and the update coefficient). A sector
+// whose chains have all stopped is skipped.
 template <typename L, int MODE, typename T, int VB>
-__global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(BondTable B, LanczosLaunch a) {
+__global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(LanczosLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int flag;
     uint32_t local = 0;
     const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
     if (s < 0) return;
     const SecWork& sw = a.secs[s];
+    if (sw.state[1] == 0) return;
+    const int step = sw.state[0];
     const SectorDev S = sw.S;
+    const BondTable& B = *sw.bonds;
     const HvLds lds = hv_lds_setup<MODE>(smem, S);
     double* wsum = lds.red;
     for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
     __syncthreads();
-    const T* x = static_cast<const T*>(sw.u[(a.step - 1) & 1]);
-    T* y = static_cast<T*>(sw.u[a.step & 1]);
+    const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
+    T* y = static_cast<T*>(sw.u[step & 1]);
     const Chain* chains = sw.chains + a.col0;
-    hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, chains,
-                                          a.step == 1, wsum);
+    hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, chains, step == 1,
+                                          wsum);
     __syncthreads();
     if (threadIdx.x < VB) {
         double t = 0.0;
@@ -231,14 +235,14 @@ hipError_t launch_hv_one(const SectorDev& s, const BondTable& B, const HvLaunch&
 }
 
 template <typename L, int MODE, typename T, int VB>
-hipError_t launch_lanczos_one(const BondTable& B, const LanczosLaunch& a, size_t lds, hipStream_t st) {
+hipError_t launch_lanczos_one(const LanczosLaunch& a, size_t lds, hipStream_t st) {
     auto kern = hv_lanczos_kernel<L, MODE, T, VB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(unsigned(a.grid)), dim3(kBlock), lds, st, B, a);
+    hipLaunchKernelGGL(kern, dim3(unsigned(a.grid)), dim3(kBlock), lds, st, a);
     return hipGetLastError();
 }
 
@@ -278,12 +282,11 @@ hipError_t launch_hv_typed(const SectorDev& s, const BondTable& B, const HvLaunc
 }
 
 template <typename T>
-hipError_t launch_lanczos_typed(int mode, int n_sites, const BondTable& B, const LanczosLaunch& a, size_t lds,
-                                hipStream_t st) {
+hipError_t launch_lanczos_typed(int mode, int n_sites, const LanczosLaunch& a, size_t lds, hipStream_t st) {
     return with_mode(mode, n_sites, [&](auto l, auto m) {
         using L = decltype(l);
         return with_vb<T>(a.vb, [&](auto vb) {
-            return launch_lanczos_one<L, decltype(m)::value, T, decltype(vb)::value>(B, a, lds, st);
+            return launch_lanczos_one<L, decltype(m)::value, T, decltype(vb)::value>(a, lds, st);
         });
     });
 }

@@ -72,15 +72,20 @@ struct HvLaunch {
     int grid;
 };
 
-// One sector of a Lanczos launch (one sector or all sectors of a plan), in
-// device memory. Its blocks are [block0, block0 + G) of the launch grid, with
-// G = rows_grid(D) so the reduction order of every column depends on D only.
+// One sector of a Lanczos launch (one sector, all sectors of a plan, or the
+// active requests of a server round), in device memory. Its blocks are
+// [block0, block0 + G) of the launch grid, with G = rows_grid(D) so the
+// reduction order of every column depends on D only. Each sector carries its
+// own bond table and step counter, so sectors of different graphs at
+// different Lanczos steps can share a launch.
 struct SecWork {
     SectorDev S;
+    const BondTable* bonds;
     void* u[2];          // [D][ld] vector blocks; step k reads u_k from u[(k-1)&1]
     Chain* chains;       // [ld]
     double* partials;    // [G][ld]
     uint32_t* ticket;
+    int32_t* state;      // [0] = current step k (1-based), [1] = chains still active
     double* alpha;       // [ld][kMaxSteps]
     double* beta;        // [ld][kMaxSteps]
     const uint64_t* keys;  // [ld] start-vector stream keys
@@ -101,7 +106,7 @@ struct LanczosLaunch {
     uint32_t col0;
     int vb;
     int dtype;
-    int step;            // k, 1-based
+    int last_chunk;      // this launch holds the last columns of a step
     double eps;          // stopping threshold
     int dist;            // start-vector distribution
     int mode;            // index mode shared by the sectors (host dispatch)
@@ -109,7 +114,7 @@ struct LanczosLaunch {
 };
 
 hipError_t launch_hv(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st);
-hipError_t launch_hv_lanczos(const BondTable& B, const LanczosLaunch& a, size_t lds, hipStream_t st);
+hipError_t launch_hv_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st);
 hipError_t launch_start(const LanczosLaunch& a, hipStream_t st);
 hipError_t launch_update(const LanczosLaunch& a, hipStream_t st);
 hipError_t launch_chain_init(const LanczosLaunch& a, hipStream_t st);

@@ -10,11 +10,11 @@
 namespace ftlm {
 
 template <typename T>
-hipError_t launch_lanczos_typed(int, int, const BondTable&, const LanczosLaunch&, size_t, hipStream_t);
+hipError_t launch_lanczos_typed(int, int, const LanczosLaunch&, size_t, hipStream_t);
 
-hipError_t launch_hv_lanczos(const BondTable& B, const LanczosLaunch& a, size_t lds, hipStream_t st) {
-    return a.dtype == 0 ? launch_lanczos_typed<float>(a.mode, a.n_sites, B, a, lds, st)
-                        : launch_lanczos_typed<double>(a.mode, a.n_sites, B, a, lds, st);
+hipError_t launch_hv_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st) {
+    return a.dtype == 0 ? launch_lanczos_typed<float>(a.mode, a.n_sites, a, lds, st)
+                        : launch_lanczos_typed<double>(a.mode, a.n_sites, a, lds, st);
 }
 
 namespace {
@@ -83,6 +83,7 @@ __global__ __launch_bounds__(kBlock) void start_kernel(LanczosLaunch a) {
             if (threadIdx.x == 0) {
                 Chain* ch = &sw.chains[col];
                 const double nrm = sqrt(tot);
+                sw.state[1] += nrm > 0.0 ? 1 : 0;
                 ch->norm = nrm;
                 ch->s_cur = nrm > 0.0 ? 1.0 / nrm : 0.0;
                 ch->s_prev = 0.0;
@@ -113,9 +114,11 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
     const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
     if (s < 0) return;
     const SecWork& sw = a.secs[s];
+    if (sw.state[1] == 0) return;
+    const int step = sw.state[0];
     const uint32_t dim = sw.S.dim;
-    const T* __restrict__ u = static_cast<const T*>(sw.u[(a.step - 1) & 1]);
-    T* __restrict__ w = static_cast<T*>(sw.u[a.step & 1]);
+    const T* __restrict__ u = static_cast<const T*>(sw.u[(step - 1) & 1]);
+    T* __restrict__ w = static_cast<T*>(sw.u[step & 1]);
     const Chain* chains = sw.chains + a.col0;
     double part[VB];
 #pragma unroll
@@ -147,12 +150,13 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
                 if (ch->active) {
                     const double bk = sqrt(tot);
                     const double ak = ch->alpha;
-                    sw.alpha[size_t(col) * kMaxSteps + (a.step - 1)] = ak;
-                    sw.beta[size_t(col) * kMaxSteps + (a.step - 1)] = bk;
+                    sw.alpha[size_t(col) * kMaxSteps + (step - 1)] = ak;
+                    sw.beta[size_t(col) * kMaxSteps + (step - 1)] = bk;
                     const double amax = fmax(ch->amax, fmax(fabs(ak), ch->beta_prev));
                     ch->amax = amax;
-                    ch->steps = a.step;
-                    if (a.step >= sw.m_eff || bk <= a.eps * amax) {
+                    ch->steps = step;
+                    if (step >= sw.m_eff || bk <= a.eps * amax) {
+                        sw.state[1] -= 1;
                         ch->active = 0;
                         ch->s_cur = 0.0;
                         ch->s_prev = 0.0;
@@ -166,11 +170,15 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
                 }
             }
         }
-        if (threadIdx.x == 0) *sw.ticket = 0u;
+        if (threadIdx.x == 0) {
+            if (a.last_chunk) sw.state[0] = step + 1;
+            *sw.ticket = 0u;
+        }
     }
 }
 
-// Zeroes every sector's chain states and ticket (one block per sector).
+// Zeroes every sector's chain states and ticket and sets its step counter to
+// 1 with no active chains (one block per sector).
 __global__ void chain_init_kernel(LanczosLaunch a) {
     if (int(blockIdx.x) >= a.nsec) return;
     const SecWork& sw = a.secs[blockIdx.x];
@@ -178,7 +186,11 @@ __global__ void chain_init_kernel(LanczosLaunch a) {
         Chain c{};
         sw.chains[i] = c;
     }
-    if (threadIdx.x == 0) *sw.ticket = 0u;
+    if (threadIdx.x == 0) {
+        *sw.ticket = 0u;
+        sw.state[0] = 1;
+        sw.state[1] = 0;
+    }
 }
 
 }  // namespace

@@ -41,13 +41,17 @@ def sector_samples(sector, graph, R, M, seed, dist, dtype, r0=0, work=None, stre
 def run(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, temps=None, g=1.0,
         batch=None, device="cuda"):
     """Full FTLM over the listed sectors. Chains run in batches of `batch`
-    (default: all R at once). Returns (thermo dict, per-sector records)."""
+    (default: all R at once; "auto": the autotuned width). Returns (thermo
+    dict, per-sector records)."""
     temps = log_temperatures() if temps is None else temps
     graph = ftlm.Graph(n_sites, bonds)
     recs = []
     for n_up in n_ups:
         sec = ftlm.Sector(n_sites, n_up, mode, device=device)
-        b = R if batch is None else batch
+        if batch == "auto":
+            b = ftlm.autotune(sec, graph, R, dtype)["batch"]
+        else:
+            b = R if batch is None else batch
         parts = []
         for r0 in range(0, R, b):
             parts.append(sector_samples(sec, graph, min(b, R - r0), M, seed, dist, dtype, r0=r0))

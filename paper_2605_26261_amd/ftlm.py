@@ -76,6 +76,15 @@ _sig("ftlm_stats_reset", _i32, [])
 _sig("ftlm_stats_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)])
 
 
+class Tuning(ctypes.Structure):
+    """ftlm_tuning."""
+    _fields_ = [("batch", ctypes.c_int32), ("n_candidates", ctypes.c_int32), ("widths", ctypes.c_int32 * 8),
+                ("ms", ctypes.c_double * 8), ("ms_per_step", ctypes.c_double), ("cached", ctypes.c_int32)]
+
+
+_sig("ftlm_autotune", _i32, [_vp, _vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(Tuning)])
+
+
 class FtlmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libftlm error {code}: {msg}")
@@ -229,6 +238,17 @@ def lanczos(sector, graph, seed, r0, R, M, dist, dtype, work=None, stream=None):
     _check(_lib.ftlm_lanczos(sector.handle, graph.handle, seed, r0, R, M, dist, dtype, _dptr(work), work.numel(),
                              _hptr(alpha), _hptr(beta), _hptr(steps), _stream(stream)))
     return alpha, beta, steps
+
+
+def autotune(sector, graph, R, dtype, work=None, stream=None):
+    """Batch width for R chains of this sector (ftlm_autotune); returns a dict."""
+    if work is None:
+        work = _empty_device(lanczos_workspace_bytes(sector, R, dtype), sector.table.device)
+    t = Tuning()
+    _check(_lib.ftlm_autotune(sector.handle, graph.handle, R, dtype, _dptr(work), work.numel(), _stream(stream),
+                              ctypes.byref(t)))
+    return {"batch": t.batch, "ms_per_step": t.ms_per_step, "cached": bool(t.cached),
+            "candidates": {t.widths[i]: t.ms[i] for i in range(t.n_candidates)}}
 
 
 def plan_workspace_bytes(graph, n_ups, mode, R, dtype):
