@@ -256,6 +256,74 @@ int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_gr
                   double* beta_host, int32_t* steps_host, void* stream);
 void ftlm_plan_destroy(ftlm_plan* p);
 
+/* ---- request server (continuous batching) ----------------------------------
+ * A server owns a worker thread that runs FTLM requests on the device out of
+ * one caller-owned arena. Requests are admitted in arrival order when their
+ * HBM footprint fits the free arena (first fit) and fewer than max_active are
+ * on the device; their tables, Krylov vectors and chain states stay on the
+ * device until they finish. Each round advances every active request by one
+ * Lanczos step, with one launch per kernel for all active requests of the
+ * same N and R (sectors of different graphs and at different steps share
+ * the launch). Finished requests leave at once and free their memory, so
+ * waiting requests are admitted while others are still running. A request's
+ * result does not depend on what else was on the device (each sector's
+ * reduction order depends only on its dimension). */
+typedef struct ftlm_server ftlm_server;
+
+typedef struct ftlm_server_opts {
+    int32_t mode;          /* FTLM_CLT or FTLM_CR */
+    int32_t dtype;         /* FTLM_F32 or FTLM_F64 */
+    int32_t max_active;    /* requests on the device at once, 1..256 (0 = 256) */
+    int32_t batch_same_n;  /* 1: one launch per step for all active requests of equal N and R */
+} ftlm_server_opts;
+
+/* One FTLM job: R chains of M Lanczos steps in the sector n_up of the graph,
+ * then E, C, chi (g) at the nT temperatures T. All arrays are copied at
+ * submission. */
+typedef struct ftlm_request {
+    int32_t n_sites;
+    int32_t n_bonds;
+    const int32_t* bi;
+    const int32_t* bj;
+    const double* J;
+    int32_t n_up;
+    int32_t R;
+    int32_t M;
+    int32_t dist;
+    uint64_t seed;
+    int32_t nT;
+    int32_t reserved;
+    const double* T;
+    double g;
+} ftlm_request;
+
+typedef struct ftlm_result_info {
+    double t_submit;  /* seconds on the server clock (ftlm_server_clock) */
+    double t_admit;
+    double t_done;
+    int32_t status;   /* FTLM_OK, or the error that ended the request */
+    int32_t steps;    /* Lanczos steps summed over the request's chains */
+    uint64_t dim;
+    uint64_t footprint;
+} ftlm_result_info;
+
+/* Device bytes a request occupies in a server arena (tables + vectors + state). */
+int ftlm_server_request_bytes(const ftlm_request* req, int mode, int dtype, size_t* bytes);
+int ftlm_server_create(void* arena_dev, size_t arena_bytes, const ftlm_server_opts* opts, ftlm_server** out);
+/* Queues a request (returns at once with its id). FTLM_E_REJECTED when its
+ * footprint exceeds the whole arena; FTLM_E_INVALID for a malformed request. */
+int ftlm_server_submit(ftlm_server* s, const ftlm_request* req, uint64_t* id);
+/* FTLM_E_AGAIN while the request is queued or running; then copies its nT
+ * values into E, C, chi, lnZ (any may be NULL), fills info and forgets it. */
+int ftlm_server_poll(ftlm_server* s, uint64_t id, double* E, double* C, double* chi, double* lnZ,
+                     ftlm_result_info* info);
+/* Seconds since the server was created (steady clock). */
+double ftlm_server_clock(const ftlm_server* s);
+/* Peak arena bytes in use and rounds run so far. */
+int ftlm_server_stats(const ftlm_server* s, uint64_t* peak_bytes, uint64_t* rounds, int32_t* active);
+/* Stops the worker after the work already on the device and frees the handle. */
+void ftlm_server_destroy(ftlm_server* s);
+
 /* ---- Ritz values and the thermal reduction (host, FP64) --------------------
  * ftlm_ritz: eigenvalues theta[m] (ascending) of the m x m symmetric
  * tridiagonal T with diagonal alpha[0..m-1] and off-diagonal beta[0..m-2],

@@ -80,6 +80,8 @@ def lib():
         L.orc_full_table.argtypes = [i32, vp, u64, vp]
         L.orc_hv_table.restype = None
         L.orc_hv_table.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, u64, u64]
+        L.orc_hv_rows_stream.restype = None
+        L.orc_hv_rows_stream.argtypes = [i32, i32, i32, vp, vp, vp, u64, u64, i32, vp, u64, vp]
         L.orc_hv_rows.restype = None
         L.orc_hv_rows.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, u64]
         L.orc_stream_key.restype = u64
@@ -217,6 +219,17 @@ def hv_rows(n_sites, n_up, bonds, x, rows, basis_arr=None):
     y = np.empty(rows.size, dtype=np.float64)
     lib().orc_hv_rows(n_sites, n_up, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), _ptr(basis_arr),
                       _ptr(x), _ptr(y), _ptr(rows), rows.size)
+    return y
+
+
+def hv_rows_stream(n_sites, n_up, bonds, seed, r, dist, rows):
+    """FP64 rows of H.x for x = the unnormalized start vector of sample r,
+    generated on demand (no full-length vector)."""
+    bi, bj, J = _bonds(bonds)
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    y = np.empty(rows.size, dtype=np.float64)
+    lib().orc_hv_rows_stream(n_sites, n_up, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), seed, r, dist, _ptr(rows),
+                             rows.size, _ptr(y))
     return y
 
 

@@ -343,3 +343,43 @@ void orc_hv_table(int n_sites, int n_up, int n_bonds, const int32_t* bi, const i
         y[r] = acc;
     }
 }
+
+/* Rows of H.x where x is the (unnormalized) start vector of sample r, each
+ * entry generated from its stream on demand, so no vector of the full
+ * sector is needed: y[k] = row rows[k] of H.x. For sectors too large to hold
+ * on the host (N = 34: 2.3e9 entries). */
+static double stream_entry(uint64_t key, uint64_t r, int dist, uint64_t i) {
+    const double two_pi = 2.0 * 3.141592653589793;
+    if (dist == 0) return (mix64(key + (i + 1) * GAMMA) >> 63) ? -1.0 : 1.0;
+    if (dist == 1) {
+        uint64_t u1 = mix64(key + (2 * i + 1) * GAMMA);
+        uint64_t u2 = mix64(key + (2 * i + 2) * GAMMA);
+        double a = (double)((u1 >> 11) + 1) * 0x1.0p-53;
+        double b = (double)(u2 >> 11) * 0x1.0p-53;
+        return sqrt(-2.0 * log(a)) * cos(two_pi * b);
+    }
+    return (i == r) ? 1.0 : 0.0;
+}
+
+void orc_hv_rows_stream(int n_sites, int n_up, int n_bonds, const int32_t* bi, const int32_t* bj,
+                        const double* J, uint64_t seed, uint64_t r, int dist, const uint64_t* rows,
+                        uint64_t nrows, double* y) {
+    uint64_t key = orc_stream_key(seed, n_up, r);
+#pragma omp parallel for schedule(dynamic, 64) if (nrows > 256)
+    for (int64_t k = 0; k < (int64_t)nrows; ++k) {
+        uint64_t t = rows[k];
+        uint64_t n = orc_unrank(n_sites, n_up, t);
+        double xt = stream_entry(key, r, dist, t);
+        double acc = 0.0;
+        for (int b = 0; b < n_bonds; ++b) {
+            int up_i = (int)((n >> bi[b]) & 1u), up_j = (int)((n >> bj[b]) & 1u);
+            double mi = up_i ? 0.5 : -0.5, mj = up_j ? 0.5 : -0.5;
+            acc += J[b] * mi * mj * xt;
+            if (up_i != up_j) {
+                uint64_t partner = n ^ (((uint64_t)1 << bi[b]) | ((uint64_t)1 << bj[b]));
+                acc += 0.5 * J[b] * stream_entry(key, r, dist, orc_rank(n_sites, n_up, partner));
+            }
+        }
+        y[k] = acc;
+    }
+}

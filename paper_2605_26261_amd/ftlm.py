@@ -85,6 +85,37 @@ class Tuning(ctypes.Structure):
 _sig("ftlm_autotune", _i32, [_vp, _vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(Tuning)])
 
 
+class ServerOpts(ctypes.Structure):
+    """ftlm_server_opts."""
+    _fields_ = [("mode", ctypes.c_int32), ("dtype", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("batch_same_n", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    """ftlm_request."""
+    _fields_ = [("n_sites", ctypes.c_int32), ("n_bonds", ctypes.c_int32), ("bi", _vp), ("bj", _vp), ("J", _vp),
+                ("n_up", ctypes.c_int32), ("R", ctypes.c_int32), ("M", ctypes.c_int32), ("dist", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("nT", ctypes.c_int32), ("reserved", ctypes.c_int32), ("T", _vp),
+                ("g", ctypes.c_double)]
+
+
+class ResultInfo(ctypes.Structure):
+    """ftlm_result_info."""
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("status", ctypes.c_int32), ("steps", ctypes.c_int32), ("dim", ctypes.c_uint64),
+                ("footprint", ctypes.c_uint64)]
+
+
+_sig("ftlm_server_request_bytes", _i32, [ctypes.POINTER(Request), _i32, _i32, ctypes.POINTER(_sz)])
+_sig("ftlm_server_create", _i32, [_vp, _sz, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)])
+_sig("ftlm_server_submit", _i32, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
+_sig("ftlm_server_poll", _i32, [_vp, ctypes.c_uint64, _vp, _vp, _vp, _vp, ctypes.POINTER(ResultInfo)])
+_sig("ftlm_server_clock", ctypes.c_double, [_vp])
+_sig("ftlm_server_stats", _i32, [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                 ctypes.POINTER(ctypes.c_int32)])
+_sig("ftlm_server_destroy", None, [_vp])
+
+
 class FtlmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libftlm error {code}: {msg}")
@@ -286,6 +317,74 @@ class Plan:
         if getattr(self, "handle", None):
             _lib.ftlm_plan_destroy(self.handle)
             self.handle = None
+
+
+def _request(n_sites, bonds, n_up, R, M, seed, dist, temps, g):
+    """ftlm_request plus the arrays it points to (kept alive by the caller)."""
+    bi = np.ascontiguousarray([b[0] for b in bonds], dtype=np.int32)
+    bj = np.ascontiguousarray([b[1] for b in bonds], dtype=np.int32)
+    J = np.ascontiguousarray([b[2] for b in bonds], dtype=np.float64)
+    T = np.ascontiguousarray(temps, dtype=np.float64)
+    q = Request(n_sites, len(bonds), bi.ctypes.data, bj.ctypes.data, J.ctypes.data, n_up, R, M, dist, seed,
+                len(T), 0, T.ctypes.data, g)
+    return q, (bi, bj, J, T)
+
+
+def server_request_bytes(n_sites, bonds, n_up, R, M, mode, dtype, temps=(1.0,)):
+    q, keep = _request(n_sites, bonds, n_up, R, M, 0, PM1, temps, 1.0)
+    n = _sz()
+    _check(_lib.ftlm_server_request_bytes(ctypes.byref(q), mode, dtype, ctypes.byref(n)))
+    return n.value
+
+
+class Server:
+    """ftlm_server: continuous-batching FTLM request server over a device arena."""
+
+    def __init__(self, arena_bytes, mode=CR, dtype=F32, max_active=0, batch_same_n=True, device="cuda"):
+        self.arena = _empty_device(arena_bytes, device)
+        opts = ServerOpts(mode, dtype, max_active, 1 if batch_same_n else 0)
+        h = _vp()
+        _check(_lib.ftlm_server_create(_dptr(self.arena), self.arena.numel(), ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h
+        self.nT = {}
+
+    def submit(self, n_sites, bonds, n_up, R, M, seed, dist, temps, g=1.0):
+        q, keep = _request(n_sites, bonds, n_up, R, M, seed, dist, temps, g)
+        rid = ctypes.c_uint64()
+        _check(_lib.ftlm_server_submit(self.handle, ctypes.byref(q), ctypes.byref(rid)))
+        self.nT[rid.value] = len(keep[3])
+        return rid.value
+
+    def poll(self, rid):
+        """None while pending; else dict E, C, chi, lnZ, t_submit, t_admit, t_done, steps, dim."""
+        n = self.nT[rid]
+        out = {k: np.empty(n) for k in ("E", "C", "chi", "lnZ")}
+        info = ResultInfo()
+        rc = _lib.ftlm_server_poll(self.handle, rid, _hptr(out["E"]), _hptr(out["C"]), _hptr(out["chi"]),
+                                   _hptr(out["lnZ"]), ctypes.byref(info))
+        if rc == E_AGAIN:
+            return None
+        del self.nT[rid]
+        _check(rc)
+        out.update(t_submit=info.t_submit, t_admit=info.t_admit, t_done=info.t_done, steps=info.steps,
+                   dim=info.dim, footprint=info.footprint)
+        return out
+
+    def clock(self):
+        return _lib.ftlm_server_clock(self.handle)
+
+    def stats(self):
+        peak, rounds, active = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int32()
+        _check(_lib.ftlm_server_stats(self.handle, ctypes.byref(peak), ctypes.byref(rounds), ctypes.byref(active)))
+        return {"peak_bytes": peak.value, "rounds": rounds.value, "active": active.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.ftlm_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 def ritz(alpha, beta, m=None):

@@ -194,3 +194,21 @@ def test_icosidodecahedron_fp32_against_fp64_reference(env):
         for key in ("E", "C"):
             _close_obs(got[key], np.array(ref[key]))
         del sec
+
+
+def test_autotune_choice_does_not_change_results(env):
+    torch, ftlm, driver = env
+    n, n_up, R = 20, 10, 12
+    bonds = graphs.dodecahedron()
+    g = ftlm.Graph(n, bonds)
+    sec = ftlm.Sector(n, n_up, ftlm.CR)
+    t = ftlm.autotune(sec, g, R, ftlm.F32)
+    assert t["batch"] in t["candidates"] and set(t["candidates"]) == {1, 2, 4, 8}
+    assert not t["cached"]
+    t2 = ftlm.autotune(sec, g, R, ftlm.F32)
+    assert t2["cached"] and t2["batch"] == t["batch"]
+    _, auto = driver.run(n, bonds, [n_up], R, 30, 7, ftlm.PM1, batch="auto")
+    for b in (None, 1, 5):
+        _, fixed = driver.run(n, bonds, [n_up], R, 30, 7, ftlm.PM1, batch=b)
+        np.testing.assert_array_equal(auto[0]["alpha"], fixed[0]["alpha"])
+        np.testing.assert_array_equal(auto[0]["beta"], fixed[0]["beta"])

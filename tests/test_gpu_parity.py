@@ -278,3 +278,32 @@ def test_start_vectors_match_oracle(env, dist, dtype):
         else:
             np.testing.assert_array_equal(got[:, c], want)
         assert abs(norms[c] - math.sqrt(float(np.dot(got[:, c], got[:, c])))) <= 1e-12 * norms[c]
+
+
+def test_hv_n34_rows_sampled(env):
+    # The largest single sector: J1-J2 ring N = 34 (J1 = 1, J2 = 0.3, 68 bonds),
+    # S^z = 0, D = 2,333,606,220 > 2^31, combinatorial ranking only. x is the
+    # +-1 start vector of sample 0 (exact in FP32); the oracle evaluates rows
+    # of H.x with x generated on demand.
+    torch, ftlm = env
+    n, n_up = 34, 17
+    bonds = graphs.j1j2_ring(n, 1.0, 0.3)
+    g = ftlm.Graph(n, bonds)
+    sec = ftlm.Sector(n, n_up, ftlm.CR)
+    d = sec.dim
+    assert d == 2333606220
+    work = torch.empty(ftlm.lanczos_workspace_bytes(sec, 1, ftlm.F32), dtype=torch.uint8, device="cuda")
+    x = torch.empty(d, dtype=torch.float32, device="cuda")
+    norms = ftlm.start_vectors(sec, 5, 0, 1, ftlm.PM1, x, work)
+    assert abs(norms[0] - math.sqrt(d)) < 1e-6 * math.sqrt(d)
+    del work
+    y = torch.empty_like(x)
+    ftlm.hv(sec, g, x, y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(34)
+    rows = np.unique(np.concatenate([rng.integers(0, d, 20000), [0, 1, 2 ** 31 - 1, 2 ** 31, 2 ** 32 - 2 ** 20, d - 1]]))
+    got = y[torch.from_numpy(rows.astype(np.int64)).cuda()].double().cpu().numpy()
+    want = oracle.hv_rows_stream(n, n_up, bonds, 5, 0, oracle.PM1, rows.astype(np.uint64))
+    assert _rel_l2(got, want) <= 1e-6
+    # the +-1 entries and J in {1, 0.3}: each row is a short sum; FP32 keeps it
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-5)

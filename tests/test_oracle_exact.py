@@ -326,3 +326,15 @@ def test_full_table_and_block_definitions_agree():
     m2, p2 = oracle.clt_blocks(n, n_up, blocks)
     np.testing.assert_array_equal(mask, m2)
     np.testing.assert_array_equal(prefix, p2)
+
+
+def test_hv_rows_on_streamed_vectors():
+    # generating x on demand gives the rows of H.x on the stored vector
+    n, n_up = 14, 6
+    bonds = graphs.random_cluster(n, np.random.default_rng(12))
+    b = oracle.basis(n, n_up)
+    for dist in (oracle.PM1, oracle.GAUSS):
+        x = oracle.start_vector(8, n_up, 3, dist, len(b), normalize=False)
+        rows = np.array([0, 17, 1000, len(b) - 1], dtype=np.uint64)
+        np.testing.assert_allclose(oracle.hv_rows_stream(n, n_up, bonds, 8, 3, dist, rows),
+                                   oracle.hv(n, n_up, bonds, x, b)[rows.astype(int)], rtol=0, atol=1e-12)
