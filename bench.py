@@ -128,6 +128,137 @@ def run_gpu(args):
     return results, n_bonds
 
 
+def plan_vs_plain():
+    """The batched all-sector workload (6x4 J1-J2 lattice, 13 sectors, R = 32
+    +-1 chains per sector, M = 80): one hipGraph-captured plan (one launch per
+    kernel per step over all sectors) against the plain form (one sector and
+    one chain at a time, eager). FTLM samples/s each."""
+    import numpy as np
+    import torch
+
+    from ftlm_inputs import graphs
+    from paper_2605_26261_amd import driver, ftlm
+
+    n, R, M, seed = 24, 32, 80, 3
+    bonds = graphs.square_j1j2(6, 4, 1.0, 0.5)
+    g = ftlm.Graph(n, bonds)
+    n_ups = list(range(12, 25))
+    plan = ftlm.Plan(g, n_ups, ftlm.CR, R, M, ftlm.F32)
+    plan.run(seed, ftlm.PM1, use_graph=True)  # capture + warm up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = driver.plan_records(plan, n, seed, ftlm.PM1, use_graph=True)
+    ftlm.thermo(n, recs, driver.log_temperatures(), 1.0)
+    t_plan = time.perf_counter() - t0
+    del plan
+    torch.cuda.empty_cache()
+    # plain: every chain alone (B = 1), sector by sector, eager launches;
+    # timed on a subset of chains per sector and scaled to all 416 samples
+    per = 4
+    t0 = time.perf_counter()
+    for nu in n_ups:
+        sec = ftlm.Sector(n, nu, ftlm.CR)
+        work = torch.empty(ftlm.lanczos_workspace_bytes(sec, 1, ftlm.F32), dtype=torch.uint8, device="cuda")
+        for r in range(per):
+            driver.sector_samples(sec, g, 1, M, seed, ftlm.PM1, ftlm.F32, r0=r, work=work)
+        del sec, work
+    t_plain = (time.perf_counter() - t0) * R / per
+    samples = R * len(n_ups)
+    return {"workload": "6x4 J1-J2 lattice (N=24, J2=0.5), all 13 sectors, R=32 +-1, M=80, FP32",
+            "plan_graph_s": t_plan, "plan_samples_per_s": samples / t_plan,
+            "plain_s_estimated": t_plain, "plain_samples_per_s": samples / t_plain,
+            "plain_protocol": f"one chain per launch, sector by sector, eager; {per} of {R} chains per sector timed"}
+
+
+def serving(n_warm=10, n_meas=60, rate=50.0):
+    """Poisson-arriving exchange-fit requests (N in 16..28, random clusters,
+    J in [0.2, 1.5], one random sector, R = 16, M = 80) through the
+    continuous-batching server; p50/p99 latency (arrival to result) and
+    samples/s, and the plain form (FIFO, one request at a time, one chain per
+    launch) on the same requests."""
+    import numpy as np
+    import torch
+
+    from ftlm_inputs.requests import exchange_fit_stream
+    from paper_2605_26261_amd import driver, ftlm
+
+    reqs = exchange_fit_stream(n_warm + n_meas, seed=4, rate=rate)
+    temps = driver.log_temperatures()
+    srv = ftlm.Server(48 << 30, mode=ftlm.CR, dtype=ftlm.F32)
+    t0 = srv.clock()
+    pending, done, k = {}, {}, 0
+    while len(done) < len(reqs):
+        now = srv.clock() - t0
+        while k < len(reqs) and reqs[k]["t"] <= now:
+            q = reqs[k]
+            pending[srv.submit(q["n_sites"], q["bonds"], q["n_up"], q["R"], q["M"], q["seed"], ftlm.PM1, temps)] = k
+            k += 1
+        for rid in list(pending):
+            r = srv.poll(rid)
+            if r is not None:
+                done[pending.pop(rid)] = r
+        time.sleep(0.0005)
+    stats = srv.stats()
+    srv.close()
+    meas = [done[i] for i in range(n_warm, len(reqs))]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in meas]) * 1e3
+    span = max(r["t_done"] for r in meas) - min(r["t_submit"] for r in meas)
+    served_sps = 16 * len(meas) / span
+    # plain FIFO: service time of each request alone with one chain per launch
+    service = []
+    for q in reqs[n_warm:]:
+        t1 = time.perf_counter()
+        driver.run(q["n_sites"], q["bonds"], [q["n_up"]], q["R"], q["M"], q["seed"], ftlm.PM1, batch=1, temps=temps)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t1)
+    finish, lat_plain = 0.0, []
+    for q, sv in zip(reqs[n_warm:], service):
+        finish = max(finish, q["t"]) + sv
+        lat_plain.append((finish - q["t"]) * 1e3)
+    plain_span = finish - reqs[n_warm]["t"]
+    return {"workload": f"Poisson {rate:g}/s exchange-fit stream, N in 16..28, R=16, M=80, FP32; "
+                        f"{n_warm} warm-up + {n_meas} measured requests",
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "samples_per_s": served_sps, "peak_arena_bytes": stats["peak_bytes"], "rounds": stats["rounds"],
+            "plain_p50_ms": float(np.percentile(lat_plain, 50)), "plain_p99_ms": float(np.percentile(lat_plain, 99)),
+            "plain_samples_per_s": 16 * len(service) / plain_span,
+            "plain_protocol": "FIFO, one request at a time, one chain per launch (latencies from measured service times)"}
+
+
+def largest_sector():
+    """J1-J2 ring N = 34 (J2 = 0.3), S^z = 0, D = 2,333,606,220, CR only: H.x
+    at B = 1 and B = 4 (the four Gaussian chains' block)."""
+    import torch
+
+    from ftlm_inputs import graphs
+    from paper_2605_26261_amd import ftlm
+
+    n = 34
+    g = ftlm.Graph(n, graphs.j1j2_ring(n, 1.0, 0.3))
+    sec = ftlm.Sector(n, 17, ftlm.CR)
+    d = sec.dim
+    out = {"workload": "J1-J2 ring N=34 S^z=0 (D=2333606220, 68 bonds), CR, FP32"}
+    for B in (1, 4):
+        x = torch.empty((d, B) if B > 1 else (d,), dtype=torch.float32, device="cuda").fill_(0.5)
+        y = torch.empty_like(x)
+        ftlm.hv(sec, g, x, y)
+        torch.cuda.synchronize()
+        ftlm.stats_reset()
+        ftlm.stats_enable(True)
+        for _ in range(2):
+            ftlm.hv(sec, g, x, y)
+        torch.cuda.synchronize()
+        ftlm.stats_enable(False)
+        nl, ms = ftlm.stats_read()
+        ms /= nl
+        out[f"hv_B{B}_ms"] = ms
+        out[f"hv_B{B}_states_bonds_per_s"] = d * g.n_bonds * B / (ms * 1e-3)
+        out[f"hv_B{B}_alg_gbs"] = 8 * d * B / (ms * 1e-3) / 1e9
+        del x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle's H.x on a bounded row sample of the same sector."""
     import numpy as np
@@ -155,8 +286,8 @@ def cpu_baseline(target_s=15.0):
 def profile_kernels():
     """Short run for hardware-counter passes: per index map, one 3-step
     Lanczos run over the 20-chain block (3 Lanczos-epilogue H.x launches and 3
-    updates) and 3 single-vector H.x launches; then a plain device copy of
-    2 GiB (reads 2 GiB, writes 2 GiB) to calibrate the byte counters."""
+    updates) and 3 single-vector H.x launches; then an elementwise kernel that
+    reads 2 GiB and writes 2 GiB, to calibrate the byte counters."""
     import torch
 
     from ftlm_inputs import graphs
@@ -174,10 +305,11 @@ def profile_kernels():
         torch.cuda.synchronize()
         del sec, x, y
         torch.cuda.empty_cache()
+    # calibration: an elementwise kernel that reads 2 GiB and writes 2 GiB
     a = torch.empty(512 << 20, dtype=torch.float32, device=dev).fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(3):
-        b.copy_(a)
+        torch.add(a, 1.0, out=b)
     torch.cuda.synchronize()
     log("profile run done")
 
@@ -188,6 +320,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true", help="skip the plan, serving and N=34 measurements")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="measured requests of the serving stream (the full stream is 2000 after 200 warm-up)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short kernel-only run for rocprofv3 counter passes")
     args = ap.parse_args()
@@ -227,6 +362,18 @@ def main():
         "modes": results,
         "roofline": roof,
     }
+    if not args.only_headline:
+        import torch
+        torch.cuda.empty_cache()
+        out["batched_all_sector"] = plan_vs_plain()
+        log("plan", json.dumps(out["batched_all_sector"]))
+        torch.cuda.empty_cache()
+        n_warm = 200 if args.serve_requests >= 2000 else 10
+        out["serving"] = serving(n_warm=n_warm, n_meas=args.serve_requests)
+        log("serving", json.dumps(out["serving"]))
+        torch.cuda.empty_cache()
+        out["largest_sector"] = largest_sector()
+        log("n34", json.dumps(out["largest_sector"]))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
