@@ -68,6 +68,10 @@ extern "C" {
 
 #define FTLM_NONE UINT64_MAX
 
+#define FTLM_SPLIT_AUTO 0   /* two-pass H.x when a vector block outgrows the L2 caches */
+#define FTLM_SPLIT_ALWAYS 1 /* whenever the graph has a split and D >= 2048 */
+#define FTLM_SPLIT_NEVER 2
+
 typedef struct ftlm_graph ftlm_graph;
 typedef struct ftlm_sector ftlm_sector;
 
@@ -91,6 +95,27 @@ int ftlm_graph_create(int n_sites, int n_bonds, const int32_t* bi, const int32_t
 void ftlm_graph_destroy(ftlm_graph* g);
 int ftlm_graph_n_sites(const ftlm_graph* g);
 int ftlm_graph_n_bonds(const ftlm_graph* g);
+
+/* ftlm_graph_split: the two-pass site split chosen for the graph's H.x (an
+ * implementation choice, not from the paper). The row-wise gather of Eq. 12
+ * reads the partner row of every antiparallel bond; in the increasing-label
+ * order of the sector a bond touching a high site sends the partner far from
+ * its row, so a single pass re-reads x from HBM. The library labels the sites
+ * so that [0, c) | [c, s) | [s, N) separates the bonds: every bond lies inside
+ * [0, s) or joins [s, N) to [0, c) or to itself. A first pass then applies the
+ * bonds inside [0, s) to rows in index order, and a second pass the others to
+ * blocks of rows that share their digits on [c, s); every block holds its rows'
+ * partners and fits in on-chip cache. site_order (host int32[N], may be null)
+ * receives the position of each of the caller's sites in that labelling; *c
+ * and *s receive the split (both 0 when the graph has none). Relabelling a
+ * graph with site_order gives a graph whose split keeps its own labels. */
+int ftlm_graph_split(const ftlm_graph* g, int32_t* site_order, int32_t* c, int32_t* s);
+
+/* ftlm_set_split_policy: FTLM_SPLIT_AUTO (default), _ALWAYS or _NEVER, for
+ * the H.x launches and Lanczos runs set up after the call (process-wide; the
+ * choice changes the summation order of rows, not the result beyond
+ * rounding). */
+int ftlm_set_split_policy(int policy);
 
 /* ---- S^z sector -------------------------------------------------------
  * ftlm_sector_table_bytes: device bytes the sector tables need. Both modes
@@ -152,7 +177,9 @@ int ftlm_neighbors(const ftlm_sector* s, const ftlm_graph* g, uint64_t t0, uint6
  * state n_t as
  *   y[t] = sum_b J_b s^z_i s^z_j x[t] + sum_{b antiparallel} (J_b / 2) x[idx(n_t ^ mask_b)]
  * with s^z_i s^z_j = +-1/4, no atomics. dtype FTLM_F32 accumulates each row in
- * FP32, FTLM_F64 in FP64. x and y must not overlap. 1 <= nvec <= 64. */
+ * FP32, FTLM_F64 in FP64. x and y must not overlap. 1 <= nvec <= 64. When the
+ * graph's split keeps the caller's labels (ftlm_graph_split) and the policy
+ * allows, the product runs in two passes (the second adds into y). */
 int ftlm_hv(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, void* y_dev, int nvec,
             int dtype, void* stream);
 
@@ -193,7 +220,10 @@ int ftlm_lanczos_workspace_bytes(const ftlm_sector* s, int R, int dtype, size_t*
  * min(M, D) or beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}), with eps =
  * 1e-6 (FP32) or 1e-12 (FP64). Outputs (host, synchronizes): alpha_host and
  * beta_host [R][M] (row r holds chain r; entries past steps_host[r] are 0),
- * steps_host[R]. 1 <= R <= 64, 1 <= M <= 4096. */
+ * steps_host[R]. 1 <= R <= 64, 1 <= M <= 4096. With the two-pass H.x the
+ * chains run in the split's site labelling; start-vector entries stay keyed
+ * by the state's index in the caller's labels, so the chains are the same up
+ * to rounding. */
 int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint64_t r0, int R,
                  int M, int dist, int dtype, void* work_dev, size_t work_bytes, double* alpha_host,
                  double* beta_host, int32_t* steps_host, void* stream);
@@ -201,12 +231,14 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
 /* ---- autotuning of the batch width -------------------------------------------
  * The B chains of a Lanczos batch share each row's index work (Sec. 2,
  * batched Lanczos; the paper picks B adaptively, Sec. 3.4). ftlm_autotune
- * times the multi-vector H.x of the sector at candidate batch widths
- * B in {1, 2, 4, 8, 16, 20, 32} (B <= R) with HIP events on `stream`, using
+ * times one Lanczos step of B chains of the sector (the multi-vector H.x in
+ * the form ftlm_lanczos would run it, and the vector update) at candidate
+ * batch widths B in {1, 2, 4, 8, 16, 20, 32} (B <= R) with HIP events on
+ * `stream`, using
  * work_dev (at least ftlm_lanczos_workspace_bytes(s, R, dtype) bytes) as
  * scratch, and returns the B that minimizes the time of one Lanczos step of
  * all R chains run in ceil(R / B) batches. Results are cached per (N, n_up,
- * bonds, mode, dtype, R) for the life of the process; the file named by the
+ * bonds, mode, dtype, R, split policy) for the life of the process; the file named by the
  * environment variable FTLM_AUTOTUNE_CACHE, when set, is read and appended
  * (one "key batch ms" line per entry). The workgroup grid is not tuned: it
  * fixes the FP64 reduction order, so results never depend on the choice. */
@@ -214,7 +246,7 @@ typedef struct ftlm_tuning {
     int32_t batch;          /* chains per ftlm_lanczos call */
     int32_t n_candidates;
     int32_t widths[8];      /* candidate B */
-    double ms[8];           /* measured H.x milliseconds at each B */
+    double ms[8];           /* measured step milliseconds at each B */
     double ms_per_step;     /* predicted step time of all R chains at `batch` */
     int32_t cached;         /* 1 when served from the cache */
 } ftlm_tuning;

@@ -55,33 +55,14 @@ int ftlm_graph_create(int n_sites, int n_bonds, const int32_t* bi, const int32_t
             g->J[size_t(it->second)] += J[b];
         }
     }
-    // Kernel bond table: sorted by the lower site, highest first.
-    const int nb = int(g->bi.size());
-    std::vector<int> order(static_cast<size_t>(nb));
-    for (int b = 0; b < nb; ++b) order[size_t(b)] = b;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-        if (g->bi[size_t(a)] != g->bi[size_t(c)]) return g->bi[size_t(a)] > g->bi[size_t(c)];
-        return g->bj[size_t(a)] > g->bj[size_t(c)];
-    });
-    BondTable& T = g->table;
-    std::memset(&T, 0, sizeof(T));
-    T.n_bonds = nb;
-    T.n_sites = n_sites;
     double jsum = 0.0;
-    for (int s = 0; s < nb; ++s) {
-        const int b = order[size_t(s)];
-        T.pack[s] = uint32_t(g->bi[size_t(b)]) | (uint32_t(g->bj[size_t(b)]) << 8) | (uint32_t(b) << 16);
-        T.coef_d[s] = 0.5 * g->J[size_t(b)];
-        T.coef_f[s] = float(0.5 * g->J[size_t(b)]);
-        jsum += g->J[size_t(b)];
+    std::vector<int> orig(g->bi.size());
+    for (size_t b = 0; b < g->bi.size(); ++b) {
+        orig[b] = int(b);
+        jsum += g->J[b];
     }
-    for (int p = 0; p <= kMaxSites; ++p) {
-        int c = 0;
-        for (int s = 0; s < nb; ++s) c += (int(T.pack[s] & 0xffu) >= p) ? 1 : 0;
-        T.ends[p] = uint32_t(p < n_sites ? c : 0);
-    }
-    T.jsum4_d = 0.25 * jsum;
-    T.jsum4_f = float(0.25 * jsum);
+    g->table = make_bond_table(n_sites, g->bi, g->bj, g->J, orig, jsum);
+    plan_split(g);
     *out = g;
     return ok();
 }
@@ -89,6 +70,22 @@ int ftlm_graph_create(int n_sites, int n_bonds, const int32_t* bi, const int32_t
 void ftlm_graph_destroy(ftlm_graph* g) { delete g; }
 int ftlm_graph_n_sites(const ftlm_graph* g) { return g ? g->n_sites : 0; }
 int ftlm_graph_n_bonds(const ftlm_graph* g) { return g ? int(g->bi.size()) : 0; }
+
+int ftlm_graph_split(const ftlm_graph* g, int32_t* site_order, int32_t* c, int32_t* s) {
+    if (!g || !c || !s) return fail(FTLM_E_INVALID, "null argument");
+    *c = g->split ? g->split_c : 0;
+    *s = g->split ? g->split_s : 0;
+    if (site_order)
+        for (int k = 0; k < g->n_sites; ++k) site_order[k] = g->split ? g->split_site[size_t(k)] : k;
+    return ok();
+}
+
+int ftlm_set_split_policy(int policy) {
+    if (policy != FTLM_SPLIT_AUTO && policy != FTLM_SPLIT_ALWAYS && policy != FTLM_SPLIT_NEVER)
+        return fail(FTLM_E_INVALID, "split policy %d", policy);
+    g_split_policy = policy;
+    return ok();
+}
 
 // ---- sector ---------------------------------------------------------------------
 int ftlm_sector_table_bytes(int n_sites, int n_up, int mode, size_t* bytes) {
@@ -219,11 +216,20 @@ int ftlm_hv_rows(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, v
     h.nrows = uint32_t(nrows);
     h.dtype = dtype;
     h.grid = int(rows_grid(uint32_t(nrows)));
+    // two passes when the split keeps the caller's labels (whole product only)
+    const bool split = row0 == 0 && nrows == s->dim && g->split_identity && use_split(g, s->dim, nvec, dtype);
+    h.split_c = g->split_c;
+    h.split_s = g->split_s;
     for (auto [col, vb] : column_chunks(nvec, uint64_t(nvec), dtype, {x_dev, y_dev})) {
         h.col0 = uint32_t(col);
         h.vb = vb;
         HvTimer timer(st);
-        HIP_CHECK(launch_hv(s->dev, g->table, h, st));
+        if (split) {
+            HIP_CHECK(launch_hv(s->dev, g->p1, h, st));
+            HIP_CHECK(launch_hv_split(s->dev, g->p2, h, st));
+        } else {
+            HIP_CHECK(launch_hv(s->dev, g->table, h, st));
+        }
     }
     return ok();
 }
@@ -252,7 +258,7 @@ SingleLayout single_layout(uint64_t dim, int R, int dtype) {
     l.secs = off;
     off = align256(off + sizeof(SecWork));
     l.bonds = off;
-    off = align256(off + sizeof(BondTable));
+    off = align256(off + kTablesPerGraph * sizeof(BondTable));
     l.total = off;
     return l;
 }
@@ -268,9 +274,9 @@ int check_lanczos_args(const ftlm_sector* s, int R, int dist, int dtype, void* w
     return FTLM_OK;
 }
 
-void single_job(LanczosJob& job, const ftlm_sector* s, const BondTable& bonds, int R, int M, int dtype, void* work) {
+void single_job(LanczosJob& job, const ftlm_sector* s, const ftlm_graph* g, int R, int M, int dtype, void* work) {
     const SingleLayout l = single_layout(s->dim, R, dtype);
-    job_layout(job, {s->dev}, {l.st}, work, R, M, dtype, at<SecWork>(work, l.secs), {bonds},
+    job_layout(job, {s->dev}, {l.st}, work, R, M, dtype, at<SecWork>(work, l.secs), {g},
                {at<BondTable>(work, l.bonds)}, {0});
 }
 
@@ -292,7 +298,7 @@ int ftlm_start_vectors(const ftlm_sector* s, uint64_t seed, uint64_t r0, int R, 
     if (!q_dev || !norms_host) return fail(FTLM_E_INVALID, "null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     LanczosJob job;
-    single_job(job, s, BondTable{}, R, 1, dtype, work_dev);
+    single_job(job, s, nullptr, R, 1, dtype, work_dev);
     job.secs[0].u[0] = q_dev;  // the start block goes to the caller's buffer
     if (int rc = job_start(job, seed, r0, dist, st)) return rc;
     std::vector<Chain> ch(static_cast<size_t>(R));
@@ -311,7 +317,7 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
     if (M < 1 || M > kMaxSteps) return fail(FTLM_E_RANGE, "M %d not in [1, %d]", M, kMaxSteps);
     hipStream_t st = static_cast<hipStream_t>(stream);
     LanczosJob job;
-    single_job(job, s, g->table, R, M, dtype, work_dev);
+    single_job(job, s, g, R, M, dtype, work_dev);
     if (int rc = job_start(job, seed, r0, dist, st)) return rc;
     if (int rc = job_steps(job, st)) return rc;
     if (int rc = job_collect(job, M, alpha_host, beta_host, steps_host, st)) return rc;
@@ -331,7 +337,8 @@ struct TuneCache {
 
 std::string tune_key(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype) {
     std::string k = "N" + std::to_string(s->n_sites) + "_u" + std::to_string(s->n_up) + "_m" +
-                    std::to_string(s->mode) + "_t" + std::to_string(dtype) + "_R" + std::to_string(R) + "_b";
+                    std::to_string(s->mode) + "_t" + std::to_string(dtype) + "_R" + std::to_string(R) + "_p" +
+                    std::to_string(g_split_policy) + "_b";
     // the bond structure, so that two graphs with the same size do not share entries
     uint64_t h = 1469598103934665603ull;
     for (size_t b = 0; b < g->bi.size(); ++b) {
@@ -386,9 +393,6 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
         }
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const SingleLayout l = single_layout(s->dim, R, dtype);
-    void* x = at<void>(work_dev, l.st.u0);
-    void* y = at<void>(work_dev, l.st.u1);
     const int widths[] = {1, 2, 4, 8, 16, 20, 32};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_CHECK(hipEventCreate(&e0));
@@ -398,16 +402,23 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
     int n = 0;
     for (int B : widths) {
         if (B > R || (dtype == FTLM_F64 && B > 16)) continue;
+        // B chains of the sector (their state fits the workspace sized for
+        // R >= B); two Lanczos steps per repetition, the first one a warm-up
+        LanczosJob job;
+        single_job(job, s, g, B, 3, dtype, work_dev);
         float best_ms = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
-            HIP_CHECK(hipEventRecord(e0, st));
-            if (int rc = ftlm_hv(s, g, x, y, B, dtype, stream)) {
+            int rc = job_start(job, 0, 0, FTLM_PM1, st);
+            if (rc == FTLM_OK) rc = job_steps(job, st, false, 1);
+            if (rc == FTLM_OK && hipEventRecord(e0, st) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc == FTLM_OK) rc = job_steps(job, st, false, 1);
+            if (rc == FTLM_OK && hipEventRecord(e1, st) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc == FTLM_OK && hipEventSynchronize(e1) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc != FTLM_OK) {
                 (void)hipEventDestroy(e0);
                 (void)hipEventDestroy(e1);
-                return rc;
+                return rc == FTLM_E_DEVICE ? fail(rc, "autotune: HIP error") : rc;
             }
-            HIP_CHECK(hipEventRecord(e1, st));
-            HIP_CHECK(hipEventSynchronize(e1));
             float ms = 0.f;
             HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
             if (rep > 0) best_ms = std::min(best_ms, ms);  // the first rep warms up
@@ -473,7 +484,7 @@ int plan_layout(int n_sites, int n_sectors, const int32_t* n_ups, int mode, int 
     L.secs = off;
     off = align256(off + size_t(n_sectors) * sizeof(SecWork));
     L.bonds = off;
-    off = align256(off + sizeof(BondTable));
+    off = align256(off + kTablesPerGraph * sizeof(BondTable));
     for (int i = 0; i < n_sectors; ++i) {
         size_t tb = 0;
         if (int rc = ftlm_sector_table_bytes(n_sites, n_ups[i], mode, &tb)) return rc;
@@ -547,7 +558,7 @@ int ftlm_plan_create(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, i
         p->sectors.push_back(s);
         devs.push_back(s->dev);
     }
-    job_layout(p->job, devs, L.state, arena_dev, R, M, dtype, at<SecWork>(arena_dev, L.secs), {g->table},
+    job_layout(p->job, devs, L.state, arena_dev, R, M, dtype, at<SecWork>(arena_dev, L.secs), {g},
                {at<BondTable>(arena_dev, L.bonds)}, std::vector<int>(size_t(n_sectors), 0));
     hipError_t e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);

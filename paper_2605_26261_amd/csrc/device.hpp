@@ -104,18 +104,54 @@ struct BondTable {
     __device__ __forceinline__ uint32_t orig(int b) const { return pack[b] >> 16; }
 };
 
-// Visits one row t of the sector: finds its label n_t and, for every bond,
-// either reports a parallel pair or the sector index of the flipped partner
-// n_t ^ (2^i + 2^j) (Eq. 12 at s = 1/2). The visitor receives
+// Reports every bond of the row with label n to the visitor, the partner
+// indices found with Alg. 2 (the occupancy test always passes for a flip
+// inside the sector, Sec. 2):
 //   v.flip(b, idx)  for an antiparallel bond b (b in the sorted order), and
-//   v.par(b)        for a parallel one.
-//
-// CLT mode reads n_t from the stored basis and looks partners up with Alg. 2
-// (the occupancy test always passes for a flip inside the sector, Sec. 2).
-//
-// CR mode reconstructs n_t by unranking and, in the same top-down pass over
-// the sites, ranks every partner in O(1): with K = number of up spins at
-// positions <= p, Es/Fs the sums over up positions q above p of
+//   v.par(b)        for a parallel one;
+// or, when the visitor takes groups (V::kGroup > 1), v.group(b0, idx, flips)
+// for kGroup consecutive bonds at a time. A group has no branch on the spins:
+// every lane looks up a label (its own for a parallel bond, giving its own
+// index), so the group's table loads and then its row gathers are all in
+// flight together; the visitor weighs parallel bonds by zero.
+template <typename V>
+__device__ __forceinline__ void clt_bonds(uint32_t n, const BondTable& B, const CltEntry* __restrict__ clt, V& v) {
+    int b = 0;
+    constexpr int G = V::kGroup;
+    if constexpr (G > 1) {
+        for (; b + G <= B.n_bonds; b += G) {
+            uint32_t m[G], idx[G];
+            bool anti[G];
+            CltEntry e[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const uint32_t lo = B.lo(b + g), hi = B.hi(b + g);
+                anti[g] = ((n >> lo) & 1u) != ((n >> hi) & 1u);
+                m[g] = anti[g] ? n ^ ((1u << lo) | (1u << hi)) : n;
+                e[g] = clt[m[g] >> 5];
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) idx[g] = e[g].prefix + __popc(e[g].mask & ((1u << (m[g] & 31u)) - 1u));
+            v.group(b, idx, anti);
+        }
+    }
+    for (; b < B.n_bonds; ++b) {
+        const uint32_t si = (n >> B.lo(b)) & 1u, sj = (n >> B.hi(b)) & 1u;
+        if (si != sj) {
+            const uint32_t m = n ^ ((1u << B.lo(b)) | (1u << B.hi(b)));
+            const CltEntry e = clt[m >> 5];
+            v.flip(b, e.prefix + __popc(e.mask & ((1u << (m & 31u)) - 1u)));
+        } else {
+            v.par(b);
+        }
+    }
+}
+
+// Combinatorial ranking of every partner of row t in O(1): one top-down pass
+// over the sites either unranks t (FROM_LABEL false: the digit at p is 1 when
+// the remaining rank reaches C(p, A)) or reads the digits of a known label n
+// (FROM_LABEL true), and ranks the partners on the way. With K = number of up
+// spins at positions <= p, Es/Fs the sums over up positions q above p of
 // C(q, K_q - 1) - C(q, K_q) and C(q, K_q + 1) - C(q, K_q), define
 //   up p:   X = Es - C(p, K),     Y = -C(p, K + 1) - Fs
 //   down p: X = C(p, K + 1) + Fs, Y = C(p, K) - Es.
@@ -124,54 +160,77 @@ struct BondTable {
 // hi whose K shifts by one telescopes into Es/Fs), so the partner's index is
 // t + X(lo) + Y(hi) mod 2^32. Y of the sites above p sits in LDS at
 // ylds[q * 64] (this lane's column of its wave's slab, bank-conflict free).
+// Bonds are visited at their lower site. Returns the label.
+template <typename L, bool FROM_LABEL, typename V>
+__device__ __forceinline__ L cr_bonds(uint32_t t, L n_in, int n_up, const BondTable& B, Binom C, uint32_t* ylds,
+                                      V& v) {
+    L n = 0;
+    uint32_t rem = t, Es = 0, Fs = 0;
+    int A = n_up;
+    int b = 0;
+    for (int p = B.n_sites - 1; p >= 0; --p) {
+        const uint32_t cm = C(p, A - 1), c0 = C(p, A), cp = C(p, A + 1);
+        bool one;
+        if constexpr (FROM_LABEL) one = ((n_in >> p) & 1) != 0;
+        else one = (A > 0) && (rem >= c0);
+        uint32_t X, Y;
+        if (one) {
+            X = Es - c0;
+            Y = 0u - cp - Fs;
+            Es += cm - c0;
+            Fs += cp - c0;
+            rem -= c0;
+            A -= 1;
+            n |= L(1) << p;
+        } else {
+            X = cp + Fs;
+            Y = c0 - Es;
+        }
+        ylds[p * 64] = Y;
+        const int end = int(B.ends[p]);
+        for (; b < end; ++b) {
+            const uint32_t hb = B.hi(b);
+            const uint32_t shi = uint32_t((n >> hb) & 1);
+            if (shi != uint32_t(one)) v.flip(b, t + X + ylds[hb * 64]);
+            else v.par(b);
+        }
+    }
+    return n;
+}
+
+// Visits one row t of the sector: finds its label n_t and, for every bond,
+// either reports a parallel pair or the sector index of the flipped partner
+// n_t ^ (2^i + 2^j) (Eq. 12 at s = 1/2). CLT mode reads n_t from the stored
+// basis; CR mode reconstructs it by unranking in the same pass that ranks the
+// partners.
 template <typename L, int MODE, typename V>
 __device__ __forceinline__ L visit_row(uint32_t t, int n_up, const BondTable& B, Binom C,
                                        const uint32_t* __restrict__ basis,
                                        const CltEntry* __restrict__ clt, uint32_t* ylds, V& v) {
     if constexpr (MODE == kModeClt) {
         const uint32_t n = basis[t];
-        for (int b = 0; b < B.n_bonds; ++b) {
-            const uint32_t si = (n >> B.lo(b)) & 1u, sj = (n >> B.hi(b)) & 1u;
-            if (si != sj) {
-                const uint32_t m = n ^ ((1u << B.lo(b)) | (1u << B.hi(b)));
-                const CltEntry e = clt[m >> 5];
-                v.flip(b, e.prefix + __popc(e.mask & ((1u << (m & 31u)) - 1u)));
-            } else {
-                v.par(b);
-            }
-        }
+        clt_bonds(n, B, clt, v);
         return L(n);
     } else {
-        L n = 0;
-        uint32_t rem = t, Es = 0, Fs = 0;
-        int A = n_up;
-        int b = 0;
-        for (int p = B.n_sites - 1; p >= 0; --p) {
-            const uint32_t cm = C(p, A - 1), c0 = C(p, A), cp = C(p, A + 1);
-            const bool one = (A > 0) && (rem >= c0);
-            uint32_t X, Y;
-            if (one) {
-                X = Es - c0;
-                Y = 0u - cp - Fs;
-                Es += cm - c0;
-                Fs += cp - c0;
-                rem -= c0;
-                A -= 1;
-                n |= L(1) << p;
-            } else {
-                X = cp + Fs;
-                Y = c0 - Es;
-            }
-            ylds[p * 64] = Y;
-            const int end = int(B.ends[p]);
-            for (; b < end; ++b) {
-                const uint32_t hb = B.hi(b);
-                const uint32_t shi = uint32_t((n >> hb) & 1);
-                if (shi != uint32_t(one)) v.flip(b, t + X + ylds[hb * 64]);
-                else v.par(b);
-            }
-        }
-        return n;
+        return cr_bonds<L, false>(t, L(0), n_up, B, C, ylds, v);
+    }
+}
+
+// Visits the row with label n (a sector member): returns its index t (Alg. 2
+// in CLT mode, Alg. 1 in CR mode) and reports its bonds as visit_row does.
+template <typename L, int MODE, typename V>
+__device__ __forceinline__ uint32_t visit_label(L n, int n_up, const BondTable& B, Binom C,
+                                                const CltEntry* __restrict__ clt, uint32_t* ylds, V& v) {
+    if constexpr (MODE == kModeClt) {
+        const uint32_t n32 = uint32_t(n);
+        const CltEntry e = clt[n32 >> 5];
+        const uint32_t t = e.prefix + __popc(e.mask & ((1u << (n32 & 31u)) - 1u));
+        clt_bonds(n32, B, clt, v);
+        return t;
+    } else {
+        const uint32_t t = cr_rank<L>(n, B.n_sites, n_up, C);
+        cr_bonds<L, true>(t, n, n_up, B, C, ylds, v);
+        return t;
     }
 }
 

@@ -116,31 +116,43 @@ size_t layout_state(uint64_t dim, int R, int dtype, size_t off, SectorState& st)
 
 
 // Fills job.secs for sectors whose tables are described by `devs` and whose
-// state sits at `states` inside `base`; sector i uses the bond table
-// dev_bonds[bond_of[i]] (device copy of bonds[bond_of[i]]). The descriptor
-// array goes to `dev_secs` (device). Blocks: each sector gets rows_grid(D)
-// blocks starting at a multiple of 8.
+// state sits at `states` inside `base`. Each graph contributes its bond table
+// in the caller's labels and its two split tables; a sector takes the split
+// tables when use_split() says so. The descriptor array goes to `dev_secs`
+// (device). Blocks: each sector gets rows_grid(D) blocks starting at a
+// multiple of 8.
 void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::vector<SectorState>& states,
-                void* base, int R, int M, int dtype, SecWork* dev_secs, const std::vector<BondTable>& bonds,
-                const std::vector<BondTable*>& dev_bonds, const std::vector<int>& bond_of) {
+                void* base, int R, int M, int dtype, SecWork* dev_secs, const std::vector<const ftlm_graph*>& graphs,
+                const std::vector<BondTable*>& dev_tables, const std::vector<int>& graph_of) {
     job.nsec = int(devs.size());
     job.R = R;
     job.dtype = dtype;
     job.mode = devs[0].mode;
     job.n_sites = devs[0].n_sites;
     job.dev_secs = dev_secs;
-    job.bonds = bonds;
-    job.dev_bonds = dev_bonds;
+    job.bonds.clear();
+    job.dev_bonds.clear();
+    for (size_t gi = 0; gi < graphs.size(); ++gi) {
+        const ftlm_graph* g = graphs[gi];
+        const BondTable zero{};
+        job.bonds.push_back(g ? g->table : zero);
+        job.bonds.push_back(g && g->split ? g->p1 : zero);
+        job.bonds.push_back(g && g->split ? g->p2 : zero);
+        for (int k = 0; k < kTablesPerGraph; ++k) job.dev_bonds.push_back(dev_tables[gi] + k);
+    }
     job.secs.assign(devs.size(), SecWork{});
     job.key_ptrs.clear();
     uint32_t block = 0;
     size_t lds = 0;
     job.max_steps = 0;
+    job.any_split = false;
     for (size_t i = 0; i < devs.size(); ++i) {
         SecWork& w = job.secs[i];
         const SectorState& st = states[i];
+        const int gi = graph_of[i];
+        const ftlm_graph* g = graphs[size_t(gi)];
         w.S = devs[i];
-        w.bonds = dev_bonds[size_t(bond_of[i])];
+        w.bonds = dev_tables[size_t(gi)];
         w.u[0] = at<void>(base, st.u0);
         w.u[1] = at<void>(base, st.u1);
         w.chains = at<Chain>(base, st.chains);
@@ -157,6 +169,17 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
         w.m_eff = int(std::min<uint64_t>(uint64_t(M), devs[i].dim));
         job.max_steps = std::max(job.max_steps, w.m_eff);
         lds = std::max(lds, hv_lds_bytes(devs[i]));
+        if (use_split(g, devs[i].dim, R, dtype)) {
+            w.split = 1;
+            w.split_c = g->split_c;
+            w.split_s = g->split_s;
+            w.bonds = dev_tables[size_t(gi)] + 1;
+            w.bonds2 = dev_tables[size_t(gi)] + 2;
+            w.relabel = g->split_identity ? 0 : 1;
+            for (int k = 0; k < g->n_sites; ++k) w.user_site[k] = uint8_t(g->user_site[size_t(k)]);
+            lds = std::max(lds, hv_split_lds_bytes(devs[i]));
+            job.any_split = true;
+        }
     }
     job.grid = int(block);
     job.lds = lds;
@@ -208,8 +231,10 @@ int job_steps(const LanczosJob& job, hipStream_t st, bool timed, int nsteps) {
             if (timed) {
                 HvTimer timer(st);
                 HIP_CHECK(launch_hv_lanczos(a, job.lds, st));
+                if (job.any_split) HIP_CHECK(launch_hv_split_lanczos(a, job.lds, st));
             } else {
                 HIP_CHECK(launch_hv_lanczos(a, job.lds, st));
+                if (job.any_split) HIP_CHECK(launch_hv_split_lanczos(a, job.lds, st));
             }
             HIP_CHECK(launch_update(a, st));
         }

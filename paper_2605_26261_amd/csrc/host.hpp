@@ -19,7 +19,16 @@ struct ftlm_graph {
     std::vector<double> J;
     int n_input = 0;           // bonds as given (before merging)
     std::vector<int> merged_of_input;
-    ftlm::BondTable table{};
+    ftlm::BondTable table{};   // in the caller's site labels
+    // Two-pass split (split.cpp): sites relabelled so that [0, split_c) |
+    // [split_c, split_s) | [split_s, N) separates the bonds; p1 holds the bonds
+    // inside [0, split_s) (and sum_b J_b / 4 over all bonds), p2 the others.
+    bool split = false;
+    bool split_identity = true;
+    int split_c = 0, split_s = 0;
+    std::vector<int> split_site;  // [caller's site] -> site in the split order
+    std::vector<int> user_site;   // [site in the split order] -> caller's site
+    ftlm::BondTable p1{}, p2{};
 };
 
 struct ftlm_sector {
@@ -47,6 +56,14 @@ int ok();
     } while (0)
 
 uint64_t binom_u64(int n, int k);
+
+// Bond tables and the two-pass split (split.cpp).
+BondTable make_bond_table(int n_sites, const std::vector<int>& lo, const std::vector<int>& hi,
+                          const std::vector<double>& J, const std::vector<int>& orig, double jsum_all);
+void plan_split(ftlm_graph* g);
+extern int g_split_policy;
+bool use_split(const ftlm_graph* g, uint64_t dim, int R, int dtype);
+constexpr int kTablesPerGraph = 3;  // caller's labels, split pass 1, split pass 2
 uint64_t stream_key(uint64_t seed, int n_up, uint64_t r);
 
 // ---- stats -------------------------------------------------------------------
@@ -104,6 +121,7 @@ struct LanczosJob {
     std::vector<BondTable*> dev_bonds;   // where each copy goes
     std::vector<std::pair<int, int>> chunks;
     int max_steps = 0;                   // largest m_eff over the sectors
+    bool any_split = false;              // some sector runs the two-pass H.x
 
     LanczosLaunch launch() const {
         LanczosLaunch a{};
@@ -119,9 +137,11 @@ struct LanczosJob {
     }
 };
 
+// Sector i runs with graph graphs[graph_of[i]] (null: no H.x, start vectors
+// only), whose kTablesPerGraph bond tables go to dev_tables[graph_of[i]].
 void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::vector<SectorState>& states,
-                void* base, int R, int M, int dtype, SecWork* dev_secs, const std::vector<BondTable>& bonds,
-                const std::vector<BondTable*>& dev_bonds, const std::vector<int>& bond_of);
+                void* base, int R, int M, int dtype, SecWork* dev_secs, const std::vector<const ftlm_graph*>& graphs,
+                const std::vector<BondTable*>& dev_tables, const std::vector<int>& graph_of);
 int job_start(LanczosJob& job, uint64_t seed, uint64_t r0, int dist, hipStream_t st);
 int job_steps(const LanczosJob& job, hipStream_t st, bool timed = true, int nsteps = -1);
 int job_collect(const LanczosJob& job, int M, double* alpha_host, double* beta_host, int32_t* steps_host,

@@ -1,0 +1,7 @@
+// FP32 instantiations of the second-pass (split) H.x kernels.
+#include "hv_impl.hpp"
+
+namespace ftlm {
+template hipError_t launch_split_typed<float>(const SectorDev&, const BondTable&, const HvLaunch&, hipStream_t);
+template hipError_t launch_lanczos_typed<float, true>(int, int, const LanczosLaunch&, size_t, hipStream_t);
+}  // namespace ftlm

@@ -1,0 +1,7 @@
+// FP64 instantiations of the second-pass (split) H.x kernels.
+#include "hv_impl.hpp"
+
+namespace ftlm {
+template hipError_t launch_split_typed<double>(const SectorDev&, const BondTable&, const HvLaunch&, hipStream_t);
+template hipError_t launch_lanczos_typed<double, true>(int, int, const LanczosLaunch&, size_t, hipStream_t);
+}  // namespace ftlm

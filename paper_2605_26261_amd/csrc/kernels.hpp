@@ -56,7 +56,9 @@ struct SectorDev {
     const CltEntry* clt;     // [2^N / 32] (CLT mode)
 };
 
-enum Epilogue { kEpiPlain = 0, kEpiLanczos = 1 };
+// kEpiLanczosPart: the first pass of a two-pass step writes
+// w = hv_a (H_1 u_k) - hv_b u_{k-1} and leaves <u_k, w> to the second pass.
+enum Epilogue { kEpiPlain = 0, kEpiLanczos = 1, kEpiLanczosPart = 2 };
 
 // One plain multi-vector H.x launch over rows [row0, row0 + nrows) and the
 // columns [col0, col0 + vb) of [D][ld] blocks x (input) and y (output).
@@ -70,6 +72,8 @@ struct HvLaunch {
     int vb;
     int dtype;
     int grid;
+    int split_c;         // two-pass split of the sites (second pass only)
+    int split_s;
 };
 
 // One sector of a Lanczos launch (one sector, all sectors of a plan, or the
@@ -93,7 +97,17 @@ struct SecWork {
     uint32_t G;
     uint32_t block0;
     int32_t m_eff;       // min(M, D)
-    int32_t pad;
+    // Two-pass H.x (split != 0): `bonds` holds the bonds inside the sites
+    // [0, split_s) and `bonds2` those touching [split_s, N), in the split site
+    // order; start-vector entries are then keyed by the index of the state in
+    // the caller's site labels, site k of the split order being the caller's
+    // site user_site[k] (relabel != 0).
+    int32_t split;
+    int32_t split_c;
+    int32_t split_s;
+    int32_t relabel;
+    const BondTable* bonds2;
+    uint8_t user_site[kMaxSites];
 };
 
 // Kernel arguments of the Lanczos kernels over a list of sectors. Columns
@@ -114,7 +128,9 @@ struct LanczosLaunch {
 };
 
 hipError_t launch_hv(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st);
+hipError_t launch_hv_split(const SectorDev& s, const BondTable& B2, const HvLaunch& h, hipStream_t st);
 hipError_t launch_hv_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st);
+hipError_t launch_hv_split_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st);
 hipError_t launch_start(const LanczosLaunch& a, hipStream_t st);
 hipError_t launch_update(const LanczosLaunch& a, hipStream_t st);
 hipError_t launch_chain_init(const LanczosLaunch& a, hipStream_t st);
@@ -140,6 +156,11 @@ inline size_t hv_slab_lds_bytes(int n_sites, int mode) {
 }
 inline size_t hv_lds_bytes(const SectorDev& s) {
     return hv_red_bytes() + hv_binom_lds_bytes(s.n_sites, s.bw, s.mode) + hv_slab_lds_bytes(s.n_sites, s.mode);
+}
+// The second pass of a two-pass H.x enumerates its rows with the binomial
+// table in both indexing modes.
+inline size_t hv_split_lds_bytes(const SectorDev& s) {
+    return hv_red_bytes() + hv_binom_lds_bytes(s.n_sites, s.bw, kModeCr) + hv_slab_lds_bytes(s.n_sites, s.mode);
 }
 
 // Grid of the persistent row kernels for a row count: a multiple of 8 (one

@@ -7,8 +7,15 @@ namespace ftlm {
 template <typename T>
 hipError_t launch_hv_typed(const SectorDev&, const BondTable&, const HvLaunch&, hipStream_t);
 
+template <typename T>
+hipError_t launch_split_typed(const SectorDev&, const BondTable&, const HvLaunch&, hipStream_t);
+
 hipError_t launch_hv(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st) {
     return h.dtype == 0 ? launch_hv_typed<float>(s, B, h, st) : launch_hv_typed<double>(s, B, h, st);
+}
+
+hipError_t launch_hv_split(const SectorDev& s, const BondTable& B2, const HvLaunch& h, hipStream_t st) {
+    return h.dtype == 0 ? launch_split_typed<float>(s, B2, h, st) : launch_split_typed<double>(s, B2, h, st);
 }
 
 namespace {
@@ -116,8 +123,13 @@ __global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDev S, const uin
 struct NeighborVisitor {
     uint64_t* out;
     const BondTable& B;
+    static constexpr int kGroup = 2;
     __device__ __forceinline__ void flip(int b, uint32_t idx) { out[B.orig(b)] = idx; }
     __device__ __forceinline__ void par(int b) { out[B.orig(b)] = ~uint64_t(0); }
+    __device__ __forceinline__ void group(int b0, const uint32_t (&idx)[kGroup], const bool (&anti)[kGroup]) {
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) out[B.orig(b0 + g)] = anti[g] ? uint64_t(idx[g]) : ~uint64_t(0);
+    }
 };
 
 template <typename L, int MODE>

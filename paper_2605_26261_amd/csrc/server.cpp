@@ -67,7 +67,7 @@ int request_layout(int n_sites, int n_up, int R, int mode, int dtype, ReqLayout&
     L.secwork = off;
     off = align256(off + sizeof(SecWork));
     L.bonds = off;
-    off = align256(off + sizeof(BondTable));
+    off = align256(off + kTablesPerGraph * sizeof(BondTable));
     if (int rc = ftlm_sector_table_bytes(n_sites, n_up, mode, &L.table_bytes)) return rc;
     L.table = off;
     off = align256(off + L.table_bytes);
@@ -173,7 +173,7 @@ int ftlm_server::admit(const std::shared_ptr<Request>& r) {
     if (int rc = ftlm_sector_create(r->n_sites, r->n_up, opts.mode, base + L.table, L.table_bytes, stream, &r->sector))
         return rc;
     job_layout(r->job, {r->sector->dev}, {L.st}, base, r->R, r->M, opts.dtype,
-               reinterpret_cast<SecWork*>(base + L.secwork), {r->graph->table},
+               reinterpret_cast<SecWork*>(base + L.secwork), {r->graph},
                {reinterpret_cast<BondTable*>(base + L.bonds)}, {0});
     if (int rc = job_start(r->job, r->seed, 0, r->dist, stream)) return rc;
     r->t_admit = now();
@@ -246,6 +246,7 @@ int ftlm_server::round() {
             block = (block + w.G + 7) & ~7u;
             g.secs.push_back(w);
             g.lds = std::max(g.lds, r->job.lds);
+            g.any_split = g.any_split || r->job.any_split;
         }
         g.grid = int(block);
         // equal R and 256-byte aligned blocks give every member the same chunks

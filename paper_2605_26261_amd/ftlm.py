@@ -51,6 +51,8 @@ _sig("ftlm_graph_create", _i32, [_i32, _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]
 _sig("ftlm_graph_destroy", None, [_vp])
 _sig("ftlm_graph_n_sites", _i32, [_vp])
 _sig("ftlm_graph_n_bonds", _i32, [_vp])
+_sig("ftlm_graph_split", _i32, [_vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+_sig("ftlm_set_split_policy", _i32, [_i32])
 _sig("ftlm_sector_table_bytes", _i32, [_i32, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("ftlm_sector_create", _i32, [_i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)])
 _sig("ftlm_sector_dim", _u64, [_vp])
@@ -155,6 +157,14 @@ def version():
     return _lib.ftlm_version()
 
 
+SPLIT_AUTO, SPLIT_ALWAYS, SPLIT_NEVER = 0, 1, 2
+
+
+def set_split_policy(policy):
+    """ftlm_set_split_policy (process-wide; later launches and runs)."""
+    _check(_lib.ftlm_set_split_policy(policy))
+
+
 class Graph:
     """ftlm_graph: bonds [(i, j, J)] on n_sites sites."""
 
@@ -170,6 +180,13 @@ class Graph:
     @property
     def n_bonds(self):
         return _lib.ftlm_graph_n_bonds(self.handle)
+
+    def split(self):
+        """ftlm_graph_split: (site_order int32[N], c, s) of the two-pass H.x."""
+        order = np.zeros(self.n_sites, dtype=np.int32)
+        c, s = _i32(), _i32()
+        _check(_lib.ftlm_graph_split(self.handle, _hptr(order), ctypes.byref(c), ctypes.byref(s)))
+        return order, c.value, s.value
 
     def __del__(self):
         if getattr(self, "handle", None):

@@ -98,6 +98,13 @@ def test_square4x6_all_sectors_against_reference(env):
     # dimension 1 to 2,704,156, +-1 vectors, seed 3, M = 80) as one plan with
     # R = 32 chains per sector; its first two chains per sector against the
     # stored FP64 oracle reference (chains do not depend on the batch).
+    #
+    # The one-magnon sector (D = 24) has 7 distinct eigenvalues, so an FP64
+    # chain meets an invariant subspace after 6 steps (beta_6 ~ 1e-12 of the
+    # scale) and stops. With FP32 vectors the same beta_6 is round-off of
+    # ~1e-5 of the scale, above the FP32 threshold 1e-6, and the chain may run
+    # on: there the step count is checked against the FP64 plan, and the FP32
+    # chain only has to reach the same near-zero beta first.
     path = os.path.join(GOLDEN, "square4x6_r2.json")
     if not os.path.exists(path):
         pytest.skip("reference not generated")
@@ -109,12 +116,28 @@ def test_square4x6_all_sectors_against_reference(env):
     n_ups = [s["n_up"] for s in ref["sectors"]]
     plan = ftlm.Plan(g, n_ups, ftlm.CR, 32, ref["M"], ftlm.F32)
     alpha, beta, steps = plan.run(ref["seed"], ftlm.PM1, use_graph=True)
+    del plan
+    plan64 = ftlm.Plan(g, n_ups, ftlm.CLT, 2, ref["M"], ftlm.F64)
+    a64, b64, s64 = plan64.run(ref["seed"], ftlm.PM1, use_graph=True)
+    del plan64
     recs = []
     for i, s in enumerate(ref["sectors"]):
+        full = min(ref["M"], s["dim"])
         for r, smp in enumerate(s["samples"]):
-            assert steps[i, r] == smp["steps"]
+            k = smp["steps"]
+            # FP64 vectors: the same steps, coefficients to summation order
+            assert s64[i, r] == k
+            np.testing.assert_allclose(a64[i, r, :k], smp["alpha"][:k], rtol=1e-9, atol=1e-9)
+            np.testing.assert_allclose(b64[i, r, :k - 1], smp["beta"][:k - 1], rtol=1e-9, atol=1e-9)
+            # FP32 vectors
+            if k == full:
+                assert steps[i, r] == k
+            else:
+                assert k <= steps[i, r] <= full
+                scale = max(np.abs(smp["alpha"][:k]).max(), np.abs(smp["beta"][:k]).max())
+                assert beta[i, r, k - 1] <= 1e-4 * scale
             assert abs(alpha[i, r, 0] - smp["alpha"][0]) <= 1e-6 * (abs(smp["alpha"][0]) + 1)
-            if smp["steps"] > 1:
+            if k > 1:
                 assert abs(beta[i, r, 0] - smp["beta"][0]) <= 1e-6 * (abs(smp["beta"][0]) + 1)
         recs.append(driver.records_from_coefficients(n, s["n_up"], s["dim"], alpha[i, :2], beta[i, :2], steps[i, :2]))
     th = ftlm.thermo(n, recs, np.array(ref["temps"]), 1.0)

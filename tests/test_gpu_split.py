@@ -1,0 +1,202 @@
+"""The two-pass (split) H.x and the Lanczos runs that use it, on the GPU.
+
+* H.x of a graph whose split keeps its labels: against the FP64 oracle at
+  1e-5 relative l2 (FP32) / 1e-13 (FP64), over sectors with many blocks and
+  ragged last tiles, every vector width and both indexing modes; CLT and CR
+  bit-identical; the same product as the one-pass kernel up to rounding.
+* Lanczos with the split (sites relabelled inside the library): FP64 chains
+  equal the oracle's to 1e-10 on the first steps with the same step counts
+  (so the start vectors are keyed by the caller's labels); plans and served
+  requests equal single-sector runs bit for bit.
+* The N = 30 S^z = 0 sector in split labels: sampled rows against the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from ftlm_inputs import graphs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_26261_amd import driver, ftlm
+    return torch, ftlm, driver
+
+
+@pytest.fixture
+def policy(env):
+    torch, ftlm, driver = env
+    yield ftlm.set_split_policy
+    ftlm.set_split_policy(ftlm.SPLIT_AUTO)
+
+
+def _rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _split_labelled(ftlm, n, bonds):
+    """The graph relabelled by its own split order (whose split keeps it)."""
+    order, c, s = ftlm.Graph(n, bonds).split()
+    assert s > 0
+    return [(int(order[i]), int(order[j]), J) for i, j, J in bonds], c, s
+
+
+CASES = [
+    (18, graphs.j1j2_ring(18, 1.0, 0.45), 9),
+    (20, graphs.dodecahedron(), 7),
+    (19, graphs.random_cluster(19, np.random.default_rng(7)), 10),
+]
+
+
+@pytest.mark.parametrize("n,bonds,n_up", CASES)
+@pytest.mark.parametrize("nvec", [1, 4, 8, 20])
+def test_split_hv_against_oracle(env, policy, n, bonds, n_up, nvec):
+    torch, ftlm, driver = env
+    rb, c, s = _split_labelled(ftlm, n, bonds)
+    g = ftlm.Graph(n, rb)
+    b = oracle.basis(n, n_up)
+    d = len(b)
+    assert d > 8 * 256 and d % 256 != 0
+    rng = np.random.default_rng(nvec + n)
+    x64 = rng.standard_normal((d, nvec))
+    dtypes = ((torch.float32, 1e-5), (torch.float64, 1e-13)) if nvec <= 16 else ((torch.float32, 1e-5),)
+    for dtype, tol in dtypes:
+        x = torch.from_numpy(x64).to(dtype).cuda().contiguous()
+        xs = x.double().cpu().numpy()
+        want = np.stack([oracle.hv(n, n_up, rb, xs[:, k], b) for k in range(nvec)], axis=1)
+        outs = []
+        for mode in (0, 1):
+            sec = ftlm.Sector(n, n_up, mode)
+            y = torch.full_like(x, float("nan"))
+            policy(ftlm.SPLIT_ALWAYS)
+            ftlm.hv(sec, g, x, y)
+            got = y.double().cpu().numpy()
+            assert np.all(np.isfinite(got))
+            assert _rel_l2(got, want) <= tol, (mode, dtype, _rel_l2(got, want))
+            outs.append(got)
+            # the one-pass kernel: the same product up to rounding
+            policy(ftlm.SPLIT_NEVER)
+            y1 = torch.empty_like(x)
+            ftlm.hv(sec, g, x, y1)
+            assert _rel_l2(got, y1.double().cpu().numpy()) <= tol
+        np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("n,bonds,n_up", CASES[:2])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_split_lanczos_fp64_against_oracle(env, policy, n, bonds, n_up, mode):
+    # the graph in the caller's labels: the library relabels the sites for the
+    # split, and the start vectors must still be those of the caller's labels
+    torch, ftlm, driver = env
+    g = ftlm.Graph(n, bonds)
+    order, c, s = g.split()
+    assert list(order) != list(range(n))
+    R, M, seed = 3, 30, 17
+    policy(ftlm.SPLIT_ALWAYS)
+    sec = ftlm.Sector(n, n_up, mode)
+    a, bt, st = ftlm.lanczos(sec, g, seed, 0, R, M, ftlm.GAUSS, ftlm.F64)
+    _, raw = oracle.ftlm_sector(n, n_up, bonds, R, M, seed, oracle.GAUSS)
+    for r in range(R):
+        a_o, b_o, k_o = raw[r]
+        assert st[r] == k_o
+        np.testing.assert_allclose(a[r, :20], a_o[:20], rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(bt[r, :20], b_o[:20], rtol=1e-10, atol=1e-10)
+    # FP32 vectors: the first coefficients at FP32 roundoff
+    a32, b32, _ = ftlm.lanczos(sec, g, seed, 0, R, M, ftlm.GAUSS, ftlm.F32)
+    for r in range(R):
+        a_o, b_o, _ = raw[r]
+        assert abs(a32[r, 0] - a_o[0]) <= 1e-6 * (abs(a_o[0]) + 1)
+        assert abs(b32[r, 0] - b_o[0]) <= 1e-6 * (abs(b_o[0]) + 1)
+
+
+def test_split_chains_same_alone_and_batched(env, policy):
+    torch, ftlm, driver = env
+    n, n_up = 20, 10
+    g = ftlm.Graph(n, graphs.dodecahedron())
+    policy(ftlm.SPLIT_ALWAYS)
+    for mode in (0, 1):
+        sec = ftlm.Sector(n, n_up, mode)
+        a8, b8, s8 = ftlm.lanczos(sec, g, 11, 0, 8, 25, ftlm.PM1, ftlm.F32)
+        a3, b3, s3 = ftlm.lanczos(sec, g, 11, 2, 3, 25, ftlm.PM1, ftlm.F32)
+        np.testing.assert_array_equal(a3, a8[2:5])
+        np.testing.assert_array_equal(b3, b8[2:5])
+        np.testing.assert_array_equal(s3, s8[2:5])
+
+
+def test_split_plan_equals_single_sector(env, policy):
+    torch, ftlm, driver = env
+    n = 18
+    bonds = graphs.j1j2_ring(n, 1.0, 0.45)
+    g = ftlm.Graph(n, bonds)
+    n_ups = [9, 10, 12, 16, 18]  # split and one-pass sectors in one launch
+    R, M = 4, 30
+    policy(ftlm.SPLIT_ALWAYS)
+    for mode in (0, 1):
+        plan = ftlm.Plan(g, n_ups, mode, R, M, ftlm.F32)
+        for use_graph in (False, True, True):
+            a_p, b_p, s_p = plan.run(5, ftlm.GAUSS, use_graph=use_graph)
+            for i, nu in enumerate(n_ups):
+                sec = ftlm.Sector(n, nu, mode)
+                a, b, s = ftlm.lanczos(sec, g, 5, 0, R, M, ftlm.GAUSS, ftlm.F32)
+                np.testing.assert_array_equal(s_p[i], s)
+                np.testing.assert_array_equal(a_p[i], a)
+                np.testing.assert_array_equal(b_p[i], b)
+        del plan
+
+
+def test_split_served_equals_direct(env, policy):
+    import time
+    torch, ftlm, driver = env
+    temps = oracle.log_temperatures(30)
+    policy(ftlm.SPLIT_ALWAYS)
+    reqs = [(18, graphs.random_cluster(18, np.random.default_rng(k)), 9 - (k % 2), 3 + k) for k in range(4)]
+    srv = ftlm.Server(1 << 30, mode=ftlm.CR, dtype=ftlm.F32)
+    ids = [srv.submit(n, b, nu, 4, 25, seed, ftlm.PM1, temps) for n, b, nu, seed in reqs]
+    out = {}
+    t0 = time.time()
+    while len(out) < len(ids):
+        for rid in ids:
+            if rid not in out:
+                r = srv.poll(rid)
+                if r is not None:
+                    out[rid] = r
+        assert time.time() - t0 < 120
+        time.sleep(0.001)
+    srv.close()
+    for (n, b, nu, seed), rid in zip(reqs, ids):
+        g = ftlm.Graph(n, b)
+        sec = ftlm.Sector(n, nu, ftlm.CR)
+        rec = driver.sector_samples(sec, g, 4, 25, seed, ftlm.PM1, ftlm.F32)
+        want = ftlm.thermo(n, [rec], temps, 1.0)
+        for key in ("E", "C"):
+            np.testing.assert_array_equal(out[rid][key], want[key])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_split_hv_n30_rows_sampled(env, policy, mode):
+    # the headline sector in split labels (the two-pass form under the
+    # automatic policy), exact FP64 rows from the oracle at sampled rows
+    torch, ftlm, driver = env
+    n, n_up = 30, 15
+    rb, c, s = _split_labelled(ftlm, n, graphs.icosidodecahedron())
+    g = ftlm.Graph(n, rb)
+    sec = ftlm.Sector(n, n_up, mode)
+    d = sec.dim
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn(d, 8, dtype=torch.float32, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    ftlm.hv(sec, g, x, y)
+    rows = np.unique(np.random.default_rng(0).integers(0, d, 5000).astype(np.uint64))
+    ridx = torch.from_numpy(rows.astype(np.int64)).cuda()
+    got = y.index_select(0, ridx).double().cpu().numpy()
+    for k in (0, 5):
+        xk = x[:, k].double().cpu().numpy()
+        want = oracle.hv_rows(n, n_up, rb, xk, rows)
+        assert _rel_l2(got[:, k], want) <= 1e-5
