@@ -51,6 +51,27 @@ def hv_alg_bytes(mode, dim, nvec, n, n_up):
     return b
 
 
+def split_graph(ftlm, bonds, n):
+    """The graph relabelled by its own two-pass split order, so that ftlm_hv
+    in the caller's labels runs the two-pass form (the Lanczos paths relabel
+    internally and need no such step)."""
+    order, c, s = ftlm.Graph(n, bonds).split()
+    return ftlm.Graph(n, [(int(order[i]), int(order[j]), J) for i, j, J in bonds]), (c, s)
+
+
+def timed_hv(ftlm, torch, sec, g, x, y, reps):
+    ftlm.hv(sec, g, x, y)
+    torch.cuda.synchronize()
+    ftlm.stats_reset()
+    ftlm.stats_enable(True)
+    for _ in range(reps):
+        ftlm.hv(sec, g, x, y)
+    torch.cuda.synchronize()
+    ftlm.stats_enable(False)
+    n, ms = ftlm.stats_read()
+    return ms / n
+
+
 def run_gpu(args):
     import numpy as np
     import torch
@@ -61,6 +82,7 @@ def run_gpu(args):
     dev = torch.device("cuda:0")
     bonds = graphs.icosidodecahedron()
     g = ftlm.Graph(N_SITES, bonds)
+    gs, split = split_graph(ftlm, bonds, N_SITES)
     n_bonds = g.n_bonds
     temps = driver.log_temperatures()
     results = {}
@@ -69,9 +91,20 @@ def run_gpu(args):
         dim = sec.dim
         work = torch.empty(ftlm.lanczos_workspace_bytes(sec, R, ftlm.F32), dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
+        if args.batch == "auto":
+            tune = ftlm.autotune(sec, g, R, ftlm.F32, work=work)
+            B = int(tune["batch"])
+            tuned = {str(w): round(t, 3) for w, t in tune["candidates"].items()}
+        else:
+            B, tuned = int(args.batch), None
+        batches = [(r0, min(B, R - r0)) for r0 in range(0, R, B)]
 
         def step():
-            rec = driver.sector_samples(sec, g, R, M, SEED, ftlm.GAUSS, ftlm.F32, work=work)
+            parts = [driver.sector_samples(sec, g, b, M, SEED, ftlm.GAUSS, ftlm.F32, r0=r0, work=work)
+                     for r0, b in batches]
+            rec = {k: parts[0][k] for k in ("n_up", "dim", "mult")}
+            for k in ("theta", "weight", "steps", "alpha", "beta"):
+                rec[k] = np.concatenate([p[k] for p in parts])
             th = ftlm.thermo(N_SITES, [rec], temps, 1.0)
             return rec, th
 
@@ -90,42 +123,58 @@ def run_gpu(args):
         dt = time.perf_counter() - t0
         ftlm.stats_enable(False)
         launches, hv_ms = ftlm.stats_read()
-        avg_ms = hv_ms / max(launches, 1)
-        alg = hv_alg_bytes(mode_name, dim, R, N_SITES, N_UP)
+        # every batch launches M = min(M, D) steps
+        job_alg = args.steps * M * sum(hv_alg_bytes(mode_name, dim, b, N_SITES, N_UP) for _, b in batches)
+        # the H.x of one batch of B chains alone: the roofline's launch
+        ftlm.lanczos(sec, g, SEED, 0, B, 2, ftlm.GAUSS, ftlm.F32, work=work)
+        torch.cuda.synchronize()
+        ftlm.stats_reset()
+        ftlm.stats_enable(True)
+        ftlm.lanczos(sec, g, SEED, 0, B, 12, ftlm.GAUSS, ftlm.F32, work=work)
+        torch.cuda.synchronize()
+        ftlm.stats_enable(False)
+        nb, msb = ftlm.stats_read()
+        avg_ms = msb / nb
+        alg = hv_alg_bytes(mode_name, dim, B, N_SITES, N_UP)
         results[mode_name] = {
+            "batch": B,
+            "autotune_ms": tuned,
             "seconds": dt,
             "ms_per_step": 1e3 * dt / args.steps,
             "states_bonds_per_s": dim * n_bonds * hv_count / dt,
             "samples_per_s": R * args.steps / dt,
             "hv_launches": launches,
+            "hv_job_alg_gbs": job_alg / (hv_ms * 1e-3) / 1e9,
             "hv_avg_ms": avg_ms,
-            "hv_kernel_states_bonds_per_s": dim * n_bonds * R / (avg_ms * 1e-3),
+            "hv_kernel_states_bonds_per_s": dim * n_bonds * B / (avg_ms * 1e-3),
             "hv_alg_bytes": alg,
             "hv_alg_gbs": alg / (avg_ms * 1e-3) / 1e9,
             "E0": float(rec["theta"][rec["theta"] != 0].min()),
         }
         log(mode_name, json.dumps(results[mode_name]))
-        # single-vector H.x (B = 1): the paper's per-SpMV access-pattern case
-        x = torch.randn(dim, dtype=torch.float32, device=dev)
-        y = torch.empty_like(x)
-        for _ in range(3):
-            ftlm.hv(sec, g, x, y)
-        torch.cuda.synchronize()
-        ftlm.stats_reset()
-        ftlm.stats_enable(True)
-        reps = 10
-        for _ in range(reps):
-            ftlm.hv(sec, g, x, y)
-        torch.cuda.synchronize()
-        ftlm.stats_enable(False)
-        n1, ms1 = ftlm.stats_read()
-        a1 = 8 * dim + (4 * dim + clt_touched_bytes(N_SITES, N_UP) if mode_name == "clt" else 0)
-        results[mode_name]["hv_b1_avg_ms"] = ms1 / n1
-        results[mode_name]["hv_b1_states_bonds_per_s"] = dim * n_bonds / (ms1 / n1 * 1e-3)
-        results[mode_name]["hv_b1_alg_gbs"] = a1 / (ms1 / n1 * 1e-3) / 1e9
-        del x, y, work, sec
+        # plain H.x at several widths: two-pass (graph in its split labels)
+        # and, at B = 1, the one-pass kernel in the RCM labels
+        del work
         torch.cuda.empty_cache()
-    return results, n_bonds
+        sweep = {}
+        for nv in (1, 4, 8, 16, 20, 32):
+            x = torch.randn((dim, nv) if nv > 1 else (dim,), dtype=torch.float32, device=dev)
+            y = torch.empty_like(x)
+            ms = timed_hv(ftlm, torch, sec, gs, x, y, 5)
+            a = hv_alg_bytes(mode_name, dim, nv, N_SITES, N_UP) - 4 * dim * nv  # no u_{k-1} read
+            sweep[str(nv)] = {"ms": ms, "states_bonds_per_s": dim * n_bonds * nv / (ms * 1e-3),
+                              "alg_gbs": a / (ms * 1e-3) / 1e9}
+            if nv == 1:
+                ms1 = timed_hv(ftlm, torch, sec, g, x, y, 5)
+                results[mode_name]["hv_b1_one_pass_ms"] = ms1
+                results[mode_name]["hv_b1_one_pass_states_bonds_per_s"] = dim * n_bonds / (ms1 * 1e-3)
+            del x, y
+            torch.cuda.empty_cache()
+        results[mode_name]["hv_split_sweep"] = sweep
+        log(mode_name, "hv sweep", json.dumps(sweep))
+        del sec
+        torch.cuda.empty_cache()
+    return results, n_bonds, split
 
 
 def plan_vs_plain():
@@ -283,25 +332,27 @@ def cpu_baseline(target_s=15.0):
                       f"(count-based ranks, no stored basis), {dt:.1f} s"}
 
 
-def profile_kernels():
-    """Short run for hardware-counter passes: per index map, one 3-step
-    Lanczos run over the 20-chain block (3 Lanczos-epilogue H.x launches and 3
-    updates) and 3 single-vector H.x launches; then an elementwise kernel that
-    reads 2 GiB and writes 2 GiB, to calibrate the byte counters."""
+def profile_kernels(batch):
+    """Short run for hardware-counter passes: per index map, a 3-step Lanczos
+    run over `batch` chains (3 two-pass H.x launches and 3 updates) and 3
+    single-vector two-pass H.x launches; then an elementwise kernel that reads
+    2 GiB and writes 2 GiB, to calibrate the byte counters."""
     import torch
 
     from ftlm_inputs import graphs
     from paper_2605_26261_amd import ftlm
 
     dev = torch.device("cuda:0")
-    g = ftlm.Graph(N_SITES, graphs.icosidodecahedron())
+    bonds = graphs.icosidodecahedron()
+    g = ftlm.Graph(N_SITES, bonds)
+    gs, _ = split_graph(ftlm, bonds, N_SITES)
     for mode in (ftlm.CLT, ftlm.CR):
         sec = ftlm.Sector(N_SITES, N_UP, mode, device=dev)
-        ftlm.lanczos(sec, g, SEED, 0, R, 3, ftlm.GAUSS, ftlm.F32)
+        ftlm.lanczos(sec, g, SEED, 0, batch, 3, ftlm.GAUSS, ftlm.F32)
         x = torch.randn(sec.dim, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
         for _ in range(3):
-            ftlm.hv(sec, g, x, y)
+            ftlm.hv(sec, gs, x, y)
         torch.cuda.synchronize()
         del sec, x, y
         torch.cuda.empty_cache()
@@ -323,23 +374,25 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="skip the plan, serving and N=34 measurements")
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="measured requests of the serving stream (the full stream is 2000 after 200 warm-up)")
+    ap.add_argument("--batch", default="auto", help="chains per Lanczos batch ('auto': the autotuner's choice)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short kernel-only run for rocprofv3 counter passes")
     args = ap.parse_args()
     if args.profile_kernels:
-        profile_kernels()
+        profile_kernels(8 if args.batch == "auto" else int(args.batch))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
-    results, n_bonds = run_gpu(args)
+    results, n_bonds, split = run_gpu(args)
     best = max(results, key=lambda k: results[k]["states_bonds_per_s"])
     r = results[best]
     dom = results[best]
     roof = {"bound": "hbm", "achieved": dom["hv_alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom["hv_alg_gbs"] / HBM_PEAK_GBS, "traffic": None,
-            "kernel": f"hv_kernel (Lanczos epilogue, {best.upper()}, 20 FP32 columns)",
+            "kernel": f"Lanczos H.x, {best.upper()}, {dom['batch']} FP32 columns: hv_lanczos_kernel + "
+                      f"hv_split_lanczos_kernel (two passes, split c={split[0]} s={split[1]})",
             "alg_bytes_per_launch": dom["hv_alg_bytes"], "avg_launch_ms": dom["hv_avg_ms"]}
     out = {
         "metric": METRIC,

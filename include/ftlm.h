@@ -68,9 +68,8 @@ extern "C" {
 
 #define FTLM_NONE UINT64_MAX
 
-#define FTLM_SPLIT_AUTO 0   /* two-pass H.x when a vector block outgrows the L2 caches */
-#define FTLM_SPLIT_ALWAYS 1 /* whenever the graph has a split and D >= 2048 */
-#define FTLM_SPLIT_NEVER 2
+#define FTLM_SPLIT_OFF 0 /* one-pass H.x (the default) */
+#define FTLM_SPLIT_ON 1  /* two-pass H.x whenever the graph has a split and D >= 2048 */
 
 typedef struct ftlm_graph ftlm_graph;
 typedef struct ftlm_sector ftlm_sector;
@@ -111,10 +110,12 @@ int ftlm_graph_n_bonds(const ftlm_graph* g);
  * graph with site_order gives a graph whose split keeps its own labels. */
 int ftlm_graph_split(const ftlm_graph* g, int32_t* site_order, int32_t* c, int32_t* s);
 
-/* ftlm_set_split_policy: FTLM_SPLIT_AUTO (default), _ALWAYS or _NEVER, for
- * the H.x launches and Lanczos runs set up after the call (process-wide; the
- * choice changes the summation order of rows, not the result beyond
- * rounding). */
+/* ftlm_set_split_policy: FTLM_SPLIT_OFF (default) or FTLM_SPLIT_ON, for the
+ * H.x launches and Lanczos runs set up after the call (process-wide; the
+ * choice changes the order of floating-point sums, not the result beyond
+ * rounding). On gfx950 the one-pass form measured faster on the N = 30
+ * workload: its time follows the number of scattered row fetches, which the
+ * split does not reduce, rather than the HBM re-reads it removes. */
 int ftlm_set_split_policy(int policy);
 
 /* ---- S^z sector -------------------------------------------------------
@@ -179,7 +180,8 @@ int ftlm_neighbors(const ftlm_sector* s, const ftlm_graph* g, uint64_t t0, uint6
  * with s^z_i s^z_j = +-1/4, no atomics. dtype FTLM_F32 accumulates each row in
  * FP32, FTLM_F64 in FP64. x and y must not overlap. 1 <= nvec <= 64. When the
  * graph's split keeps the caller's labels (ftlm_graph_split) and the policy
- * allows, the product runs in two passes (the second adds into y). */
+ * allows (FTLM_SPLIT_ON), the product runs in two passes (the second adds
+ * into y). */
 int ftlm_hv(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, void* y_dev, int nvec,
             int dtype, void* stream);
 

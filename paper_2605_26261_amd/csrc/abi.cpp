@@ -81,7 +81,7 @@ int ftlm_graph_split(const ftlm_graph* g, int32_t* site_order, int32_t* c, int32
 }
 
 int ftlm_set_split_policy(int policy) {
-    if (policy != FTLM_SPLIT_AUTO && policy != FTLM_SPLIT_ALWAYS && policy != FTLM_SPLIT_NEVER)
+    if (policy != FTLM_SPLIT_OFF && policy != FTLM_SPLIT_ON)
         return fail(FTLM_E_INVALID, "split policy %d", policy);
     g_split_policy = policy;
     return ok();

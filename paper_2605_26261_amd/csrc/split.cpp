@@ -11,8 +11,11 @@
 // holds all their partners); the second pass takes the others over blocks of
 // rows with equal digits on [c, s) (again closed under those bonds). Both
 // kinds of block hold at most C(s, s/2) and C(N - s + c, (N - s + c)/2) rows,
-// small enough for one XCD's L2 on the workloads of interest, so each pass
-// reads x from HBM about once.
+// which bounds how far a pass reaches for its partners. Measured on gfx950 at
+// N = 30 the pair of passes is slower than one pass: the time follows the
+// number of scattered row fetches (the same in both forms), not the HBM
+// re-reads the split removes, and the second pass's rows come in short runs.
+// The split is therefore opt-in (ftlm_set_split_policy).
 #include <algorithm>
 #include <cstring>
 
@@ -182,18 +185,15 @@ void plan_split(ftlm_graph* g) {
     g->split = true;
 }
 
-int g_split_policy = FTLM_SPLIT_AUTO;
+int g_split_policy = FTLM_SPLIT_OFF;
 
-// Whether a sector of dimension `dim` with R chains of `dtype` runs the
-// two-pass H.x: the graph has a split, the grid has one share per XCD, and
-// (automatic policy) a vector block is larger than the chip's L2 caches
-// together, below which the one-pass gathers already hit on chip.
+// Whether a sector of dimension `dim` runs the two-pass H.x: the policy asks
+// for it, the graph has a split, and the grid has one share per XCD.
 bool use_split(const ftlm_graph* g, uint64_t dim, int R, int dtype) {
-    if (!g || !g->split || g_split_policy == FTLM_SPLIT_NEVER) return false;
-    if (dim < 8 * uint64_t(kBlock)) return false;
-    if (g_split_policy == FTLM_SPLIT_ALWAYS) return true;
-    const uint64_t es = dtype == FTLM_F32 ? 4 : 8;
-    return dim * uint64_t(R) * es >= (uint64_t(32) << 20);
+    (void)R;
+    (void)dtype;
+    if (!g || !g->split || g_split_policy != FTLM_SPLIT_ON) return false;
+    return dim >= 8 * uint64_t(kBlock);
 }
 
 }  // namespace ftlm

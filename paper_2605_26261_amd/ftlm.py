@@ -157,7 +157,7 @@ def version():
     return _lib.ftlm_version()
 
 
-SPLIT_AUTO, SPLIT_ALWAYS, SPLIT_NEVER = 0, 1, 2
+SPLIT_OFF, SPLIT_ON = 0, 1
 
 
 def set_split_policy(policy):

@@ -114,7 +114,7 @@ def test_graph_split_random_and_small(ftlm):
     assert (c, s) == (0, 0)
     with pytest.raises(ftlm.FtlmError):
         ftlm.set_split_policy(7)
-    ftlm.set_split_policy(ftlm.SPLIT_AUTO)
+    ftlm.set_split_policy(ftlm.SPLIT_OFF)
 
 
 @pytest.mark.parametrize("m", [1, 2, 3, 7, 40, 100, 300])

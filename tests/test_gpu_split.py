@@ -34,7 +34,7 @@ def env():
 def policy(env):
     torch, ftlm, driver = env
     yield ftlm.set_split_policy
-    ftlm.set_split_policy(ftlm.SPLIT_AUTO)
+    ftlm.set_split_policy(ftlm.SPLIT_OFF)
 
 
 def _rel_l2(a, b):
@@ -75,14 +75,14 @@ def test_split_hv_against_oracle(env, policy, n, bonds, n_up, nvec):
         for mode in (0, 1):
             sec = ftlm.Sector(n, n_up, mode)
             y = torch.full_like(x, float("nan"))
-            policy(ftlm.SPLIT_ALWAYS)
+            policy(ftlm.SPLIT_ON)
             ftlm.hv(sec, g, x, y)
             got = y.double().cpu().numpy()
             assert np.all(np.isfinite(got))
             assert _rel_l2(got, want) <= tol, (mode, dtype, _rel_l2(got, want))
             outs.append(got)
             # the one-pass kernel: the same product up to rounding
-            policy(ftlm.SPLIT_NEVER)
+            policy(ftlm.SPLIT_OFF)
             y1 = torch.empty_like(x)
             ftlm.hv(sec, g, x, y1)
             assert _rel_l2(got, y1.double().cpu().numpy()) <= tol
@@ -99,7 +99,7 @@ def test_split_lanczos_fp64_against_oracle(env, policy, n, bonds, n_up, mode):
     order, c, s = g.split()
     assert list(order) != list(range(n))
     R, M, seed = 3, 30, 17
-    policy(ftlm.SPLIT_ALWAYS)
+    policy(ftlm.SPLIT_ON)
     sec = ftlm.Sector(n, n_up, mode)
     a, bt, st = ftlm.lanczos(sec, g, seed, 0, R, M, ftlm.GAUSS, ftlm.F64)
     _, raw = oracle.ftlm_sector(n, n_up, bonds, R, M, seed, oracle.GAUSS)
@@ -120,7 +120,7 @@ def test_split_chains_same_alone_and_batched(env, policy):
     torch, ftlm, driver = env
     n, n_up = 20, 10
     g = ftlm.Graph(n, graphs.dodecahedron())
-    policy(ftlm.SPLIT_ALWAYS)
+    policy(ftlm.SPLIT_ON)
     for mode in (0, 1):
         sec = ftlm.Sector(n, n_up, mode)
         a8, b8, s8 = ftlm.lanczos(sec, g, 11, 0, 8, 25, ftlm.PM1, ftlm.F32)
@@ -137,7 +137,7 @@ def test_split_plan_equals_single_sector(env, policy):
     g = ftlm.Graph(n, bonds)
     n_ups = [9, 10, 12, 16, 18]  # split and one-pass sectors in one launch
     R, M = 4, 30
-    policy(ftlm.SPLIT_ALWAYS)
+    policy(ftlm.SPLIT_ON)
     for mode in (0, 1):
         plan = ftlm.Plan(g, n_ups, mode, R, M, ftlm.F32)
         for use_graph in (False, True, True):
@@ -155,7 +155,7 @@ def test_split_served_equals_direct(env, policy):
     import time
     torch, ftlm, driver = env
     temps = oracle.log_temperatures(30)
-    policy(ftlm.SPLIT_ALWAYS)
+    policy(ftlm.SPLIT_ON)
     reqs = [(18, graphs.random_cluster(18, np.random.default_rng(k)), 9 - (k % 2), 3 + k) for k in range(4)]
     srv = ftlm.Server(1 << 30, mode=ftlm.CR, dtype=ftlm.F32)
     ids = [srv.submit(n, b, nu, 4, 25, seed, ftlm.PM1, temps) for n, b, nu, seed in reqs]
@@ -181,14 +181,15 @@ def test_split_served_equals_direct(env, policy):
 
 @pytest.mark.parametrize("mode", [0, 1])
 def test_split_hv_n30_rows_sampled(env, policy, mode):
-    # the headline sector in split labels (the two-pass form under the
-    # automatic policy), exact FP64 rows from the oracle at sampled rows
+    # the headline sector in split labels, two-pass form, exact FP64 rows
+    # from the oracle at sampled rows
     torch, ftlm, driver = env
     n, n_up = 30, 15
     rb, c, s = _split_labelled(ftlm, n, graphs.icosidodecahedron())
     g = ftlm.Graph(n, rb)
     sec = ftlm.Sector(n, n_up, mode)
     d = sec.dim
+    policy(ftlm.SPLIT_ON)
     gen = torch.Generator(device="cuda").manual_seed(5)
     x = torch.randn(d, 8, dtype=torch.float32, device="cuda", generator=gen)
     y = torch.empty_like(x)
