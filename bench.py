@@ -30,6 +30,23 @@ HBM_PEAK_GBS = 8000.0
 N_SITES, N_UP, R, M, SEED = 30, 15, 20, 100, 2
 
 
+# HBM bytes per steady-state launch of the dominant kernel (Lanczos-epilogue
+# H.x over 20 FP32 columns), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
+# scaled by the counts of a 2 GiB copy (profiles/hv_lanczos_n30_r20_counters.md).
+# They describe the kernel sources with this hash and are dropped otherwise.
+KERNEL_SOURCES = ["layout.hpp", "device.hpp", "kernels.hpp", "rowloop.hpp", "hv_impl.hpp", "hv_f32.hip"]
+MEASURED_TRAFFIC = {"sources": "c990b0ea17bafa2a", "batch": 20, "bytes": {"clt": 475.62e9, "cr": 343.39e9}}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_26261_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -49,14 +66,6 @@ def hv_alg_bytes(mode, dim, nvec, n, n_up):
     if mode == "clt":
         b += 4 * dim + clt_touched_bytes(n, n_up)
     return b
-
-
-def split_graph(ftlm, bonds, n):
-    """The graph relabelled by its own two-pass split order, so that ftlm_hv
-    in the caller's labels runs the two-pass form (the Lanczos paths relabel
-    internally and need no such step)."""
-    order, c, s = ftlm.Graph(n, bonds).split()
-    return ftlm.Graph(n, [(int(order[i]), int(order[j]), J) for i, j, J in bonds]), (c, s)
 
 
 def timed_hv(ftlm, torch, sec, g, x, y, reps):
@@ -82,7 +91,6 @@ def run_gpu(args):
     dev = torch.device("cuda:0")
     bonds = graphs.icosidodecahedron()
     g = ftlm.Graph(N_SITES, bonds)
-    gs, split = split_graph(ftlm, bonds, N_SITES)
     n_bonds = g.n_bonds
     temps = driver.log_temperatures()
     results = {}
@@ -152,29 +160,24 @@ def run_gpu(args):
             "E0": float(rec["theta"][rec["theta"] != 0].min()),
         }
         log(mode_name, json.dumps(results[mode_name]))
-        # plain H.x at several widths: two-pass (graph in its split labels)
-        # and, at B = 1, the one-pass kernel in the RCM labels
+        # plain H.x (ftlm_hv) at several block widths, 5 launches each
         del work
         torch.cuda.empty_cache()
         sweep = {}
         for nv in (1, 4, 8, 16, 20, 32):
             x = torch.randn((dim, nv) if nv > 1 else (dim,), dtype=torch.float32, device=dev)
             y = torch.empty_like(x)
-            ms = timed_hv(ftlm, torch, sec, gs, x, y, 5)
+            ms = timed_hv(ftlm, torch, sec, g, x, y, 5)
             a = hv_alg_bytes(mode_name, dim, nv, N_SITES, N_UP) - 4 * dim * nv  # no u_{k-1} read
             sweep[str(nv)] = {"ms": ms, "states_bonds_per_s": dim * n_bonds * nv / (ms * 1e-3),
                               "alg_gbs": a / (ms * 1e-3) / 1e9}
-            if nv == 1:
-                ms1 = timed_hv(ftlm, torch, sec, g, x, y, 5)
-                results[mode_name]["hv_b1_one_pass_ms"] = ms1
-                results[mode_name]["hv_b1_one_pass_states_bonds_per_s"] = dim * n_bonds / (ms1 * 1e-3)
             del x, y
             torch.cuda.empty_cache()
-        results[mode_name]["hv_split_sweep"] = sweep
+        results[mode_name]["hv_width_sweep"] = sweep
         log(mode_name, "hv sweep", json.dumps(sweep))
         del sec
         torch.cuda.empty_cache()
-    return results, n_bonds, split
+    return results, n_bonds
 
 
 def plan_vs_plain():
@@ -334,8 +337,8 @@ def cpu_baseline(target_s=15.0):
 
 def profile_kernels(batch):
     """Short run for hardware-counter passes: per index map, a 3-step Lanczos
-    run over `batch` chains (3 two-pass H.x launches and 3 updates) and 3
-    single-vector two-pass H.x launches; then an elementwise kernel that reads
+    run over `batch` chains (3 Lanczos-epilogue H.x launches and 3 updates)
+    and 3 single-vector H.x launches; then an elementwise kernel that reads
     2 GiB and writes 2 GiB, to calibrate the byte counters."""
     import torch
 
@@ -343,16 +346,14 @@ def profile_kernels(batch):
     from paper_2605_26261_amd import ftlm
 
     dev = torch.device("cuda:0")
-    bonds = graphs.icosidodecahedron()
-    g = ftlm.Graph(N_SITES, bonds)
-    gs, _ = split_graph(ftlm, bonds, N_SITES)
+    g = ftlm.Graph(N_SITES, graphs.icosidodecahedron())
     for mode in (ftlm.CLT, ftlm.CR):
         sec = ftlm.Sector(N_SITES, N_UP, mode, device=dev)
         ftlm.lanczos(sec, g, SEED, 0, batch, 3, ftlm.GAUSS, ftlm.F32)
         x = torch.randn(sec.dim, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
         for _ in range(3):
-            ftlm.hv(sec, gs, x, y)
+            ftlm.hv(sec, g, x, y)
         torch.cuda.synchronize()
         del sec, x, y
         torch.cuda.empty_cache()
@@ -379,20 +380,24 @@ def main():
                     help="short kernel-only run for rocprofv3 counter passes")
     args = ap.parse_args()
     if args.profile_kernels:
-        profile_kernels(8 if args.batch == "auto" else int(args.batch))
+        profile_kernels(R if args.batch == "auto" else int(args.batch))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
-    results, n_bonds, split = run_gpu(args)
+    results, n_bonds = run_gpu(args)
     best = max(results, key=lambda k: results[k]["states_bonds_per_s"])
     r = results[best]
     dom = results[best]
+    traffic = None
+    if kernel_source_hash() == MEASURED_TRAFFIC["sources"] and dom["batch"] == MEASURED_TRAFFIC["batch"]:
+        traffic = MEASURED_TRAFFIC["bytes"][best]
     roof = {"bound": "hbm", "achieved": dom["hv_alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom["hv_alg_gbs"] / HBM_PEAK_GBS, "traffic": None,
-            "kernel": f"Lanczos H.x, {best.upper()}, {dom['batch']} FP32 columns: hv_lanczos_kernel + "
-                      f"hv_split_lanczos_kernel (two passes, split c={split[0]} s={split[1]})",
+            "frac": dom["hv_alg_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM fetch + write, counter-calibrated)",
+            "kernel": f"hv_lanczos_kernel<uint32, {best.upper()}, float, {dom['batch']}> (Lanczos-epilogue H.x "
+                      f"over {dom['batch']} FP32 columns)",
             "alg_bytes_per_launch": dom["hv_alg_bytes"], "avg_launch_ms": dom["hv_avg_ms"]}
     out = {
         "metric": METRIC,
