@@ -122,10 +122,24 @@ __global__ __launch_bounds__(kBlock) void start_kernel(LanczosLaunch a) {
 // stopping rule: a chain stops after step k when k reaches min(M, D) or
 // beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}). A stopped chain gets
 // zero scales, so its columns stay zero in every later step.
+// Blocks whose rows are 48 to 96 bytes (a multiple of 16) go through LDS a
+// tile at a time: the tile's rows of u and w are contiguous, so they move with
+// fully coalesced 16-byte accesses, while each thread still updates its own
+// row (the same arithmetic and summation order as without the staging). With
+// one thread per row, a 16-byte access of rows that wide spans several cache
+// lines per wave; narrower rows are already well coalesced.
+template <typename T, int VB>
+__host__ __device__ constexpr bool update_staged() {
+    return (VB * sizeof(T)) % 16 == 0 && VB * sizeof(T) >= 48 && VB * sizeof(T) <= 96;
+}
+
 template <typename T, int VB>
 __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
     __shared__ double red[kBlock];
     __shared__ int flag;
+    constexpr bool kStage = update_staged<T, VB>();
+    __shared__ __align__(16) T stage_u[kStage ? kBlock * VB : 1];
+    __shared__ __align__(16) T stage_w[kStage ? kBlock * VB : 1];
     uint32_t local = 0;
     const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
     if (s < 0) return;
@@ -140,8 +154,41 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
 #pragma unroll
     for (int c = 0; c < VB; ++c) part[c] = 0.0;
     const uint32_t ntiles = (dim + kBlock - 1) / kBlock;
+    // whole rows of [D][ld] blocks: a tile is one contiguous range
+    const bool staged = kStage && a.col0 == 0 && a.ld == uint64_t(VB);
     for_each_tile(ntiles, local, sw.G, [&](uint32_t tile) {
         const uint32_t t = tile * kBlock + threadIdx.x;
+        if constexpr (kStage) {
+            if (staged) {
+                const uint32_t t0 = tile * kBlock;
+                const uint32_t rows = dim - t0 < uint32_t(kBlock) ? dim - t0 : uint32_t(kBlock);
+                const uint32_t n16 = rows * uint32_t(VB * sizeof(T)) / 16u;
+                const float4* gu = reinterpret_cast<const float4*>(u + uint64_t(t0) * VB);
+                float4* gw = reinterpret_cast<float4*>(w + uint64_t(t0) * VB);
+                float4* lu = reinterpret_cast<float4*>(stage_u);
+                float4* lw = reinterpret_cast<float4*>(stage_w);
+                for (uint32_t i = threadIdx.x; i < n16; i += kBlock) {
+                    lu[i] = gu[i];
+                    lw[i] = gw[i];
+                }
+                __syncthreads();
+                if (threadIdx.x < rows) {
+                    T* wr = stage_w + threadIdx.x * VB;
+                    const T* ur = stage_u + threadIdx.x * VB;
+#pragma unroll
+                    for (int c = 0; c < VB; ++c) {
+                        const T coef = sizeof(T) == 4 ? T(chains[c].up_f) : T(chains[c].up_d);
+                        const T v = wr[c] - coef * ur[c];
+                        part[c] += double(v) * double(v);
+                        wr[c] = v;
+                    }
+                }
+                __syncthreads();
+                for (uint32_t i = threadIdx.x; i < n16; i += kBlock) gw[i] = lw[i];
+                __syncthreads();
+                return;
+            }
+        }
         if (t >= dim) return;
         T uu[VB], ww[VB];
         load_row<T, VB>(u + uint64_t(t) * a.ld + a.col0, uu);
