@@ -222,7 +222,7 @@ def plan_vs_plain():
             "plain_protocol": f"one chain per launch, sector by sector, eager; {per} of {R} chains per sector timed"}
 
 
-def serving(n_warm=10, n_meas=60, rate=50.0):
+def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True):
     """Poisson-arriving exchange-fit requests (N in 16..28, random clusters,
     J in [0.2, 1.5], one random sector, R = 16, M = 80) through the
     continuous-batching server; p50/p99 latency (arrival to result) and
@@ -236,7 +236,7 @@ def serving(n_warm=10, n_meas=60, rate=50.0):
 
     reqs = exchange_fit_stream(n_warm + n_meas, seed=4, rate=rate)
     temps = driver.log_temperatures()
-    srv = ftlm.Server(48 << 30, mode=ftlm.CR, dtype=ftlm.F32)
+    srv = ftlm.Server(48 << 30, mode=ftlm.CR, dtype=ftlm.F32, max_active=max_active)
     t0 = srv.clock()
     pending, done, k = {}, {}, 0
     while len(done) < len(reqs):
@@ -256,6 +256,13 @@ def serving(n_warm=10, n_meas=60, rate=50.0):
     lat = np.array([r["t_done"] - r["t_submit"] for r in meas]) * 1e3
     span = max(r["t_done"] for r in meas) - min(r["t_submit"] for r in meas)
     served_sps = 16 * len(meas) / span
+    out = {"workload": f"Poisson {rate:g}/s exchange-fit stream, N in 16..28, R=16, M=80, FP32; "
+                       f"{n_warm} warm-up + {n_meas} measured requests",
+           "max_active": max_active or 16,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "samples_per_s": served_sps, "peak_arena_bytes": stats["peak_bytes"], "rounds": stats["rounds"]}
+    if not plain:
+        return out
     # plain FIFO: service time of each request alone with one chain per launch
     service = []
     for q in reqs[n_warm:]:
@@ -268,13 +275,12 @@ def serving(n_warm=10, n_meas=60, rate=50.0):
         finish = max(finish, q["t"]) + sv
         lat_plain.append((finish - q["t"]) * 1e3)
     plain_span = finish - reqs[n_warm]["t"]
-    return {"workload": f"Poisson {rate:g}/s exchange-fit stream, N in 16..28, R=16, M=80, FP32; "
-                        f"{n_warm} warm-up + {n_meas} measured requests",
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "samples_per_s": served_sps, "peak_arena_bytes": stats["peak_bytes"], "rounds": stats["rounds"],
-            "plain_p50_ms": float(np.percentile(lat_plain, 50)), "plain_p99_ms": float(np.percentile(lat_plain, 99)),
-            "plain_samples_per_s": 16 * len(service) / plain_span,
-            "plain_protocol": "FIFO, one request at a time, one chain per launch (latencies from measured service times)"}
+    out.update({"plain_p50_ms": float(np.percentile(lat_plain, 50)),
+                "plain_p99_ms": float(np.percentile(lat_plain, 99)),
+                "plain_samples_per_s": 16 * len(service) / plain_span,
+                "plain_protocol": "FIFO, one request at a time, one chain per launch "
+                                  "(latencies from measured service times)"})
+    return out
 
 
 def largest_sector():

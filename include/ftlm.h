@@ -307,7 +307,9 @@ typedef struct ftlm_server ftlm_server;
 typedef struct ftlm_server_opts {
     int32_t mode;          /* FTLM_CLT or FTLM_CR */
     int32_t dtype;         /* FTLM_F32 or FTLM_F64 */
-    int32_t max_active;    /* requests on the device at once, 1..256 (0 = 256) */
+    int32_t max_active;    /* requests on the device at once, 1..256 (0 = 16: a small active set
+                              finishes the oldest requests first at the same throughput, since
+                              every round still fills the device) */
     int32_t batch_same_n;  /* 1: one launch per step for all active requests of equal N and R */
 } ftlm_server_opts;
 

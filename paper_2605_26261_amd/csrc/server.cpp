@@ -29,6 +29,7 @@ using namespace ftlm;
 namespace {
 
 constexpr int kServerMaxActive = 256;
+constexpr int kServerDefaultActive = 16;
 
 struct Request {
     uint64_t id = 0;
@@ -275,7 +276,7 @@ void ftlm_server::run() {
     const size_t desc_bytes = align256(size_t(kServerMaxActive) * sizeof(SecWork));
     heap.init(desc_bytes, arena_bytes);
     const size_t max_active = size_t(opts.max_active > 0 ? std::min(opts.max_active, kServerMaxActive)
-                                                         : kServerMaxActive);
+                                                         : kServerDefaultActive);
     for (;;) {
         // admission, in arrival order
         std::vector<std::shared_ptr<Request>> admit_now;
