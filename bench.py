@@ -69,16 +69,21 @@ def hv_alg_bytes(mode, dim, nvec, n, n_up):
 
 
 def timed_hv(ftlm, torch, sec, g, x, y, reps):
+    """Median of `reps` H.x launches, each bracketed by HIP events on the
+    stream the library launches on (torch's current stream)."""
     ftlm.hv(sec, g, x, y)
     torch.cuda.synchronize()
-    ftlm.stats_reset()
-    ftlm.stats_enable(True)
+    st = torch.cuda.current_stream()
+    times = []
     for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
         ftlm.hv(sec, g, x, y)
-    torch.cuda.synchronize()
-    ftlm.stats_enable(False)
-    n, ms = ftlm.stats_read()
-    return ms / n
+        e1.record(st)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
 
 
 def run_gpu(args):
@@ -160,14 +165,14 @@ def run_gpu(args):
             "E0": float(rec["theta"][rec["theta"] != 0].min()),
         }
         log(mode_name, json.dumps(results[mode_name]))
-        # plain H.x (ftlm_hv) at several block widths, 5 launches each
+        # plain H.x (ftlm_hv) at several block widths: median of 20 launches
         del work
         torch.cuda.empty_cache()
         sweep = {}
         for nv in (1, 4, 8, 16, 20, 32):
             x = torch.randn((dim, nv) if nv > 1 else (dim,), dtype=torch.float32, device=dev)
             y = torch.empty_like(x)
-            ms = timed_hv(ftlm, torch, sec, g, x, y, 5)
+            ms = timed_hv(ftlm, torch, sec, g, x, y, 20)
             a = hv_alg_bytes(mode_name, dim, nv, N_SITES, N_UP) - 4 * dim * nv  # no u_{k-1} read
             sweep[str(nv)] = {"ms": ms, "states_bonds_per_s": dim * n_bonds * nv / (ms * 1e-3),
                               "alg_gbs": a / (ms * 1e-3) / 1e9}
@@ -285,35 +290,41 @@ def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True):
 
 def largest_sector():
     """J1-J2 ring N = 34 (J2 = 0.3), S^z = 0, D = 2,333,606,220, CR only: H.x
-    at B = 1 and B = 4 (the four Gaussian chains' block)."""
+    at B = 1 and B = 4, and the whole FTLM run of the workload (R = 4
+    Gaussian chains, seed 5, M = 60, FP32 vectors) with its samples/s."""
     import torch
 
     from ftlm_inputs import graphs
-    from paper_2605_26261_amd import ftlm
+    from paper_2605_26261_amd import driver, ftlm
 
-    n = 34
-    g = ftlm.Graph(n, graphs.j1j2_ring(n, 1.0, 0.3))
+    n, R, M, seed = 34, 4, 60, 5
+    bonds = graphs.j1j2_ring(n, 1.0, 0.3)
+    g = ftlm.Graph(n, bonds)
     sec = ftlm.Sector(n, 17, ftlm.CR)
     d = sec.dim
-    out = {"workload": "J1-J2 ring N=34 S^z=0 (D=2333606220, 68 bonds), CR, FP32"}
+    out = {"workload": "J1-J2 ring N=34 S^z=0 (D=2333606220, 68 bonds), CR, FP32; FTLM R=4 Gaussian seed 5, M=60"}
     for B in (1, 4):
         x = torch.empty((d, B) if B > 1 else (d,), dtype=torch.float32, device="cuda").fill_(0.5)
         y = torch.empty_like(x)
-        ftlm.hv(sec, g, x, y)
-        torch.cuda.synchronize()
-        ftlm.stats_reset()
-        ftlm.stats_enable(True)
-        for _ in range(2):
-            ftlm.hv(sec, g, x, y)
-        torch.cuda.synchronize()
-        ftlm.stats_enable(False)
-        nl, ms = ftlm.stats_read()
-        ms /= nl
+        ms = timed_hv(ftlm, torch, sec, g, x, y, 3)
         out[f"hv_B{B}_ms"] = ms
         out[f"hv_B{B}_states_bonds_per_s"] = d * g.n_bonds * B / (ms * 1e-3)
         out[f"hv_B{B}_alg_gbs"] = 8 * d * B / (ms * 1e-3) / 1e9
         del x, y
         torch.cuda.empty_cache()
+    work = torch.empty(ftlm.lanczos_workspace_bytes(sec, R, ftlm.F32), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec = driver.sector_samples(sec, g, R, M, seed, ftlm.GAUSS, ftlm.F32, work=work)
+    th = ftlm.thermo(n, [rec], driver.log_temperatures(), 1.0)
+    dt = time.perf_counter() - t0
+    out["ftlm_s"] = dt
+    out["ftlm_samples_per_s"] = R / dt
+    out["ftlm_states_bonds_per_s"] = d * g.n_bonds * int(rec["steps"].sum()) / dt
+    out["E0"] = float(rec["theta"][rec["theta"] != 0].min())
+    out["E_per_site_T0.5"] = float(th["E"][int(abs(driver.log_temperatures() - 0.5).argmin())] / n)
+    del work, sec
+    torch.cuda.empty_cache()
     return out
 
 
