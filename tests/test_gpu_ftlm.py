@@ -212,3 +212,33 @@ def test_autotune_choice_does_not_change_results(env):
         _, fixed = driver.run(n, bonds, [n_up], R, 30, 7, ftlm.PM1, batch=b)
         np.testing.assert_array_equal(auto[0]["alpha"], fixed[0]["alpha"])
         np.testing.assert_array_equal(auto[0]["beta"], fixed[0]["beta"])
+
+
+def test_icosidodecahedron_twenty_column_block(env):
+    # The launch configuration the benchmark times: all 20 chains of the
+    # N = 30 workload in one block. Its first two chains equal the 2-chain run
+    # bit for bit (a chain does not depend on its batch) and agree with the
+    # stored FP64 oracle reference at FP32 roundoff, in both index maps.
+    path = os.path.join(GOLDEN, "icosidodecahedron_r2.json")
+    if not os.path.exists(path):
+        pytest.skip("reference not generated")
+    torch, ftlm, driver = env
+    ref = json.load(open(path))
+    n, n_up, M = ref["n_sites"], ref["n_up"], 6
+    g = ftlm.Graph(n, [tuple(b) for b in ref["bonds"]])
+    for mode in (ftlm.CLT, ftlm.CR):
+        sec = ftlm.Sector(n, n_up, mode)
+        a20, b20, s20 = ftlm.lanczos(sec, g, ref["seed"], 0, 20, M, ftlm.GAUSS, ftlm.F32)
+        a2, b2, s2 = ftlm.lanczos(sec, g, ref["seed"], 0, 2, M, ftlm.GAUSS, ftlm.F32)
+        np.testing.assert_array_equal(a20[:2], a2)
+        np.testing.assert_array_equal(b20[:2], b2)
+        np.testing.assert_array_equal(s20[:2], s2)
+        for r, smp in enumerate(ref["samples"]):
+            assert abs(a20[r, 0] - smp["alpha"][0]) <= 1e-6 * abs(smp["alpha"][0])
+            assert abs(b20[r, 0] - smp["beta"][0]) <= 1e-6 * abs(smp["beta"][0])
+        # every chain: alpha_1 = <r|H|r> lies inside the spectrum's range
+        # (|E| <= sum_b |J_b| / 4 * 3) and beta_1 > 0
+        assert np.all(np.abs(a20[:, 0]) <= 0.75 * len(ref["bonds"]))
+        assert np.all(b20[:, 0] > 0)
+        del sec
+        torch.cuda.empty_cache()
