@@ -14,6 +14,27 @@ namespace ftlm {
 
 constexpr uint32_t kNone32 = 0xFFFFFFFFu;
 
+// Global-memory accesses through a generic pointer. Every table and vector
+// block the kernels touch is device memory, in the global address space;
+// saying so lets the compiler emit global instead of flat instructions where
+// the pointer came out of a device-memory descriptor (a flat load also holds
+// up every LDS wait until it completes).
+#define FTLM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const FTLM_GLOBAL T* gptr(const T* p) {
+    return (const FTLM_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ FTLM_GLOBAL T* gptr(T* p) {
+    return (FTLM_GLOBAL T*)p;
+}
+
+// One compressed-lookup-table entry, read as a single 8-byte global load.
+__device__ __forceinline__ CltEntry clt_entry(const CltEntry* clt, uint32_t block) {
+    const FTLM_GLOBAL CltEntry* q = gptr(clt + block);
+    return CltEntry{q->mask, q->prefix};
+}
+
 template <typename L>
 __device__ __forceinline__ int popc(L x) {
     if constexpr (sizeof(L) == 8) return __popcll(x);
@@ -32,7 +53,7 @@ struct Binom {
 // Copies the sector's binomial table from HBM into LDS (all threads of the
 // block take part; ends with a barrier).
 __device__ __forceinline__ void stage_binomials(uint32_t* lds, const uint32_t* g, int count) {
-    for (int i = threadIdx.x; i < count; i += blockDim.x) lds[i] = g[i];
+    for (int i = threadIdx.x; i < count; i += blockDim.x) lds[i] = *gptr(g + i);
     __syncthreads();
 }
 
@@ -77,7 +98,7 @@ __device__ __forceinline__ uint32_t cr_rank(L x, int n_sites, int n_up, Binom C)
 // Alg. 2: index of label n through the compressed lookup table, kNone32 when
 // bit n mod 32 of the block's mask is clear.
 __device__ __forceinline__ uint32_t clt_lookup(const CltEntry* clt, uint32_t n) {
-    CltEntry e = clt[n >> 5];
+    CltEntry e = clt_entry(clt, n >> 5);
     uint32_t j = n & 31u;
     if (((e.mask >> j) & 1u) == 0) return kNone32;
     return e.prefix + __popc(e.mask & ((1u << j) - 1u));
@@ -110,7 +131,8 @@ struct BondTable {
 //   v.flip(b, idx)  for an antiparallel bond b (b in the sorted order), and
 //   v.par(b)        for a parallel one;
 // or, when the visitor takes groups (V::kGroup > 1), v.group(b0, idx, flips)
-// for kGroup consecutive bonds at a time. A group has no branch on the spins:
+// for kGroup consecutive bonds at a time (CLT), and v.site_group(b0, idx,
+// flips, count) for up to V::kSiteGroup bonds of one lower site (CR). A group has no branch on the spins:
 // every lane looks up a label (its own for a parallel bond, giving its own
 // index), so the group's table loads and then its row gathers are all in
 // flight together; the visitor weighs parallel bonds by zero.
@@ -128,7 +150,7 @@ __device__ __forceinline__ void clt_bonds(uint32_t n, const BondTable& B, const 
                 const uint32_t lo = B.lo(b + g), hi = B.hi(b + g);
                 anti[g] = ((n >> lo) & 1u) != ((n >> hi) & 1u);
                 m[g] = anti[g] ? n ^ ((1u << lo) | (1u << hi)) : n;
-                e[g] = clt[m[g] >> 5];
+                e[g] = clt_entry(clt, m[g] >> 5);
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) idx[g] = e[g].prefix + __popc(e[g].mask & ((1u << (m[g] & 31u)) - 1u));
@@ -139,7 +161,7 @@ __device__ __forceinline__ void clt_bonds(uint32_t n, const BondTable& B, const 
         const uint32_t si = (n >> B.lo(b)) & 1u, sj = (n >> B.hi(b)) & 1u;
         if (si != sj) {
             const uint32_t m = n ^ ((1u << B.lo(b)) | (1u << B.hi(b)));
-            const CltEntry e = clt[m >> 5];
+            const CltEntry e = clt_entry(clt, m >> 5);
             v.flip(b, e.prefix + __popc(e.mask & ((1u << (m & 31u)) - 1u)));
         } else {
             v.par(b);
@@ -188,11 +210,34 @@ __device__ __forceinline__ L cr_bonds(uint32_t t, L n_in, int n_up, const BondTa
         }
         ylds[p * 64] = Y;
         const int end = int(B.ends[p]);
-        for (; b < end; ++b) {
-            const uint32_t hb = B.hi(b);
-            const uint32_t shi = uint32_t((n >> hb) & 1);
-            if (shi != uint32_t(one)) v.flip(b, t + X + ylds[hb * 64]);
-            else v.par(b);
+        if constexpr (V::kSiteGroup > 1) {
+            // the bonds whose lower site is p, V::kSiteGroup at a time: their
+            // gathers go out together before any of them is consumed
+            constexpr int G = V::kSiteGroup;
+            for (; b < end; b += G) {
+                const int cnt = end - b < G ? end - b : G;
+                uint32_t idx[G];
+                bool anti[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    anti[g] = false;
+                    idx[g] = t;
+                    if (g < cnt) {
+                        const uint32_t hb = B.hi(b + g);
+                        anti[g] = uint32_t((n >> hb) & 1) != uint32_t(one);
+                        if (anti[g]) idx[g] = t + X + ylds[hb * 64];
+                    }
+                }
+                v.site_group(b, idx, anti, cnt);
+            }
+            b = end;
+        } else {
+            for (; b < end; ++b) {
+                const uint32_t hb = B.hi(b);
+                const uint32_t shi = uint32_t((n >> hb) & 1);
+                if (shi != uint32_t(one)) v.flip(b, t + X + ylds[hb * 64]);
+                else v.par(b);
+            }
         }
     }
     return n;
@@ -208,7 +253,7 @@ __device__ __forceinline__ L visit_row(uint32_t t, int n_up, const BondTable& B,
                                        const uint32_t* __restrict__ basis,
                                        const CltEntry* __restrict__ clt, uint32_t* ylds, V& v) {
     if constexpr (MODE == kModeClt) {
-        const uint32_t n = basis[t];
+        const uint32_t n = *gptr(basis + t);
         clt_bonds(n, B, clt, v);
         return L(n);
     } else {
@@ -223,7 +268,7 @@ __device__ __forceinline__ uint32_t visit_label(L n, int n_up, const BondTable& 
                                                 const CltEntry* __restrict__ clt, uint32_t* ylds, V& v) {
     if constexpr (MODE == kModeClt) {
         const uint32_t n32 = uint32_t(n);
-        const CltEntry e = clt[n32 >> 5];
+        const CltEntry e = clt_entry(clt, n32 >> 5);
         const uint32_t t = e.prefix + __popc(e.mask & ((1u << (n32 & 31u)) - 1u));
         clt_bonds(n32, B, clt, v);
         return t;

@@ -10,25 +10,28 @@
 namespace ftlm {
 
 // Loads/stores VB consecutive elements with the widest naturally aligned
-// vector access (the host only picks a vector width whose alignment holds).
+// vector access (the host only picks a vector width whose alignment holds),
+// as global-memory accesses.
+template <typename T, int N>
+using VecT = T __attribute__((ext_vector_type(N)));
+
 template <typename T, int VB>
 __device__ __forceinline__ void load_row(const T* __restrict__ p, T (&v)[VB]) {
     if constexpr (sizeof(T) == 4 && VB % 4 == 0) {
 #pragma unroll
         for (int i = 0; i < VB; i += 4) {
-            const float4 q = *reinterpret_cast<const float4*>(p + i);
+            const VecT<T, 4> q = *(const FTLM_GLOBAL VecT<T, 4>*)(p + i);
             v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
         }
     } else if constexpr (VB % 2 == 0) {
-        using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
 #pragma unroll
         for (int i = 0; i < VB; i += 2) {
-            const V2 q = *reinterpret_cast<const V2*>(p + i);
+            const VecT<T, 2> q = *(const FTLM_GLOBAL VecT<T, 2>*)(p + i);
             v[i] = q.x; v[i + 1] = q.y;
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < VB; ++i) v[i] = p[i];
+        for (int i = 0; i < VB; ++i) v[i] = *gptr(p + i);
     }
 }
 
@@ -36,19 +39,19 @@ template <typename T, int VB>
 __device__ __forceinline__ void store_row(T* __restrict__ p, const T (&v)[VB]) {
     if constexpr (sizeof(T) == 4 && VB % 4 == 0) {
 #pragma unroll
-        for (int i = 0; i < VB; i += 4)
-            *reinterpret_cast<float4*>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+        for (int i = 0; i < VB; i += 4) {
+            const VecT<T, 4> q = {v[i], v[i + 1], v[i + 2], v[i + 3]};
+            *(FTLM_GLOBAL VecT<T, 4>*)(p + i) = q;
+        }
     } else if constexpr (VB % 2 == 0) {
-        using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
 #pragma unroll
         for (int i = 0; i < VB; i += 2) {
-            V2 q;
-            q.x = v[i]; q.y = v[i + 1];
-            *reinterpret_cast<V2*>(p + i) = q;
+            const VecT<T, 2> q = {v[i], v[i + 1]};
+            *(FTLM_GLOBAL VecT<T, 2>*)(p + i) = q;
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < VB; ++i) p[i] = v[i];
+        for (int i = 0; i < VB; ++i) *gptr(p + i) = v[i];
     }
 }
 
@@ -88,6 +91,33 @@ struct GatherVisitor {
     // bond's index is the row itself), then accumulated with weight J_b / 2
     // or zero.
     static constexpr int kGroup = VB >= 16 ? 2 : 4;
+    static constexpr int kSiteGroup = VB > 20 ? 1 : (VB >= 16 ? 2 : 4);
+    // Up to kSiteGroup bonds of one lower site (count is wave-uniform): the
+    // rows of the antiparallel ones are loaded together (lanes whose bond is
+    // parallel load nothing), then accumulated in bond order.
+    __device__ __forceinline__ void site_group(int b0, const uint32_t (&idx)[kSiteGroup],
+                                               const bool (&flips)[kSiteGroup], int count) {
+        T v[kSiteGroup][VB];
+#pragma unroll
+        for (int g = 0; g < kSiteGroup; ++g) {
+#pragma unroll
+            for (int i = 0; i < VB; ++i) v[g][i] = T(0);
+            if (g < count && flips[g]) {
+                const uint32_t i = idx[g] < last ? idx[g] : last;
+                load_row<T, VB>(x + uint64_t(i) * ld + col0, v[g]);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kSiteGroup; ++g) {
+            if (g < count) {
+                const T cb = bond_coef<T>(B, b0 + g);
+            const T c = flips[g] ? cb : T(0);
+#pragma unroll
+                for (int i = 0; i < VB; ++i) acc[i] += c * v[g][i];
+                anti += c;
+            }
+        }
+    }
     __device__ __forceinline__ void group(int b0, const uint32_t (&idx)[kGroup], const bool (&flips)[kGroup]) {
         T v[kGroup][VB];
 #pragma unroll
@@ -97,7 +127,8 @@ struct GatherVisitor {
         }
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-            const T c = flips[g] ? bond_coef<T>(B, b0 + g) : T(0);
+            const T cb = bond_coef<T>(B, b0 + g);
+            const T c = flips[g] ? cb : T(0);
 #pragma unroll
             for (int i = 0; i < VB; ++i) acc[i] += c * v[g][i];
             anti += c;
@@ -128,13 +159,13 @@ __device__ __forceinline__ HvLds hv_lds_setup(unsigned char* smem, const SectorD
 // The rows of one block of a (sub-)grid of G blocks: y = H x on rows
 // [row0, row0 + nrows), columns [col0, col0 + VB) of [D][ld] blocks. In the
 // Lanczos epilogue y holds u_{k-1} on entry (unless `first`) and receives
-// w = hv_a (H u_k) - hv_b u_{k-1} per column; the products u_k[t] w[t] are
+// w = hv_a (H u_k) - hv_b u_{k-1} per column (ab = [hv_a | hv_b], VB each); the products u_k[t] w[t] are
 // folded, tile by tile, into per-wave FP64 sums wsum[wave * VB + c] (LDS).
 template <typename L, int MODE, typename T, int VB, int EPI>
 __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, const HvLds& lds,
                                         const T* __restrict__ x, T* __restrict__ y, uint64_t ld,
                                         uint32_t col0, uint32_t row0, uint32_t nrows, uint32_t bid,
-                                        uint32_t G, const Chain* chains, bool first, double* wsum) {
+                                        uint32_t G, const T* ab, bool first, double* wsum) {
     const Binom C{lds.binom, S.bw};
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const T jsum4 = sizeof(T) == 4 ? T(B.jsum4_f) : T(B.jsum4_d);
@@ -166,9 +197,7 @@ __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, 
                 }
 #pragma unroll
                 for (int c = 0; c < VB; ++c) {
-                    const T a = sizeof(T) == 4 ? T(chains[c].hv_a_f) : T(chains[c].hv_a_d);
-                    const T b = sizeof(T) == 4 ? T(chains[c].hv_b_f) : T(chains[c].hv_b_d);
-                    out[c] = a * out[c] - b * z[c];
+                    out[c] = ab[c] * out[c] - ab[VB + c] * z[c];
                 }
             }
             store_row<T, VB>(yrow, out);
@@ -192,6 +221,28 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, Hv
     const HvLds lds = hv_lds_setup<MODE>(smem, S);
     hv_body<L, MODE, T, VB, kEpiPlain>(S, B, lds, static_cast<const T*>(h.x), static_cast<T*>(h.y), h.ld, h.col0,
                                         h.row0, h.nrows, blockIdx.x, gridDim.x, nullptr, false, nullptr);
+}
+
+// The Lanczos kernels find their bond table through the sector descriptor in
+// device memory, a generic pointer to the compiler; a copy in a static LDS
+// object turns every bond read of the row loop into a broadcast LDS read. (The
+// plain kernel gets the table as a kernel argument, read with scalar loads.)
+// Visible after the caller's next barrier.
+__device__ __forceinline__ void stage_bonds(BondTable& dst, const BondTable* src) {
+    uint32_t* d = reinterpret_cast<uint32_t*>(&dst);
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
+    for (int i = threadIdx.x; i < int(sizeof(BondTable) / 4); i += kBlock) d[i] = *gptr(w + i);
+}
+
+// The epilogue scalars [hv_a | hv_b] of columns [col0, col0 + VB), in the
+// vector precision, into LDS; visible after the caller's next barrier.
+template <typename T, int VB>
+__device__ __forceinline__ void stage_epilogue(T* ab, const Chain* chains) {
+    if (threadIdx.x < VB) {
+        const Chain* ch = chains + threadIdx.x;
+        ab[threadIdx.x] = sizeof(T) == 4 ? T(ch->hv_a_f) : T(ch->hv_a_d);
+        ab[VB + threadIdx.x] = sizeof(T) == 4 ? T(ch->hv_b_f) : T(ch->hv_b_d);
+    }
 }
 
 // Publishes this block's <u_k, w> sums (per-wave FP64 sums in wsum) and, in
@@ -230,27 +281,30 @@ __global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(LanczosLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int flag;
     uint32_t local = 0;
-    const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
+    const SecWork* secs = a.secs;
+    const int s = sector_of_block(secs, a.nsec, blockIdx.x, &local);
     if (s < 0) return;
-    const SecWork& sw = a.secs[s];
+    const SecWork& sw = secs[s];
     if (sw.state[1] == 0) return;
     const int step = sw.state[0];
     const SectorDev S = sw.S;
-    const BondTable& B = *sw.bonds;
+    __shared__ BondTable B;
+    __shared__ T ab[2 * VB];
+    stage_bonds(B, sw.bonds);
+    stage_epilogue<T, VB>(ab, sw.chains + a.col0);
     const HvLds lds = hv_lds_setup<MODE>(smem, S);
     double* wsum = lds.red;
     for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
     __syncthreads();
     const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
     T* y = static_cast<T*>(sw.u[step & 1]);
-    const Chain* chains = sw.chains + a.col0;
     if (sw.split) {
         // first pass of a two-pass step: the bonds inside [0, split_s)
-        hv_body<L, MODE, T, VB, kEpiLanczosPart>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, chains,
+        hv_body<L, MODE, T, VB, kEpiLanczosPart>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, ab,
                                                   step == 1, nullptr);
         return;
     }
-    hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, chains, step == 1,
+    hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, ab, step == 1,
                                           wsum);
     alpha_tail<VB>(sw, a, wsum, lds.red, local, &flag);
 }
@@ -327,7 +381,7 @@ struct SplitSched {
 template <typename L, int MODE, typename T, int VB, int EPI>
 __device__ __forceinline__ void hv_split_body(const SectorDev& S, const BondTable& B2, const HvLds& lds, int c,
                                               int s, const T* __restrict__ x, T* __restrict__ y, uint64_t ld,
-                                              uint32_t col0, uint32_t bid, uint32_t G, const Chain* chains,
+                                              uint32_t col0, uint32_t bid, uint32_t G, const T* ab,
                                               double* wsum) {
     const Binom C{lds.binom, S.bw};
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -359,8 +413,7 @@ __device__ __forceinline__ void hv_split_body(const SectorDev& S, const BondTabl
             for (int i = 0; i < VB; ++i) {
                 const T h = acc[i] - anti * xt[i];
                 if constexpr (EPI == kEpiLanczos) {
-                    const T a = sizeof(T) == 4 ? T(chains[i].hv_a_f) : T(chains[i].hv_a_d);
-                    out[i] = z[i] + a * h;
+                    out[i] = z[i] + ab[i] * h;
                 } else {
                     out[i] = z[i] + h;
                 }
@@ -395,20 +448,25 @@ __global__ __launch_bounds__(kBlock) void hv_split_lanczos_kernel(LanczosLaunch 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int flag;
     uint32_t local = 0;
-    const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
+    const SecWork* secs = a.secs;
+    const int s = sector_of_block(secs, a.nsec, blockIdx.x, &local);
     if (s < 0) return;
-    const SecWork& sw = a.secs[s];
+    const SecWork& sw = secs[s];
     if (!sw.split || sw.state[1] == 0) return;
     const int step = sw.state[0];
     const SectorDev S = sw.S;
+    __shared__ BondTable B2;
+    __shared__ T ab[2 * VB];
+    stage_bonds(B2, sw.bonds2);
+    stage_epilogue<T, VB>(ab, sw.chains + a.col0);
     const HvLds lds = hv_lds_setup<MODE, true>(smem, S);
     double* wsum = lds.red;
     for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
     __syncthreads();
     const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
     T* y = static_cast<T*>(sw.u[step & 1]);
-    hv_split_body<L, MODE, T, VB, kEpiLanczos>(S, *sw.bonds2, lds, sw.split_c, sw.split_s, x, y, a.ld, a.col0,
-                                                local, sw.G, sw.chains + a.col0, wsum);
+    hv_split_body<L, MODE, T, VB, kEpiLanczos>(S, B2, lds, sw.split_c, sw.split_s, x, y, a.ld,
+                                                a.col0, local, sw.G, ab, wsum);
     alpha_tail<VB>(sw, a, wsum, lds.red, local, &flag);
 }
 

@@ -148,20 +148,21 @@ hipError_t launch_neighbors(const SectorDev& s, const BondTable& B, uint64_t t0,
 // LDS bytes of the H.x kernels: FP64 scratch, then (CR) the binomial table
 // and one [site][lane] slab of Y values per wave.
 __host__ __device__ constexpr size_t hv_red_bytes() { return kBlock * sizeof(double); }
-inline size_t hv_binom_lds_bytes(int n_sites, int bw, int mode) {
+__host__ __device__ inline size_t hv_binom_lds_bytes(int n_sites, int bw, int mode) {
     return mode == kModeCr ? ((size_t(n_sites) * size_t(bw) * 4 + 15) & ~size_t(15)) : 0;
 }
-inline size_t hv_slab_lds_bytes(int n_sites, int mode) {
+__host__ __device__ inline size_t hv_slab_lds_bytes(int n_sites, int mode) {
     return mode == kModeCr ? size_t(kWaves) * size_t(n_sites) * 64 * 4 : 0;
 }
-inline size_t hv_lds_bytes(const SectorDev& s) {
+__host__ __device__ inline size_t hv_lds_bytes(const SectorDev& s) {
     return hv_red_bytes() + hv_binom_lds_bytes(s.n_sites, s.bw, s.mode) + hv_slab_lds_bytes(s.n_sites, s.mode);
 }
 // The second pass of a two-pass H.x enumerates its rows with the binomial
 // table in both indexing modes.
-inline size_t hv_split_lds_bytes(const SectorDev& s) {
+__host__ __device__ inline size_t hv_split_lds_bytes(const SectorDev& s) {
     return hv_red_bytes() + hv_binom_lds_bytes(s.n_sites, s.bw, kModeCr) + hv_slab_lds_bytes(s.n_sites, s.mode);
 }
+
 
 // Grid of the persistent row kernels for a row count: a multiple of 8 (one
 // share per XCD) capped near the number of resident workgroups, so reduction
