@@ -215,23 +215,27 @@ __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, 
     });
 }
 
-template <typename L, int MODE, typename T, int VB>
-__global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, HvLaunch h) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const HvLds lds = hv_lds_setup<MODE>(smem, S);
-    hv_body<L, MODE, T, VB, kEpiPlain>(S, B, lds, static_cast<const T*>(h.x), static_cast<T*>(h.y), h.ld, h.col0,
-                                        h.row0, h.nrows, blockIdx.x, gridDim.x, nullptr, false, nullptr);
-}
-
-// The Lanczos kernels find their bond table through the sector descriptor in
-// device memory, a generic pointer to the compiler; a copy in a static LDS
-// object turns every bond read of the row loop into a broadcast LDS read. (The
-// plain kernel gets the table as a kernel argument, read with scalar loads.)
-// Visible after the caller's next barrier.
+// Every H.x kernel reads its bond table from a copy in a static LDS object:
+// the row loop's bond reads become broadcast LDS reads, which lets the
+// compiler keep several partner rows in flight per thread (read from kernel
+// arguments or through a generic pointer, the table costs scalar or flat
+// loads whose waits serialise the gathers). Visible after the caller's next
+// barrier.
 __device__ __forceinline__ void stage_bonds(BondTable& dst, const BondTable* src) {
     uint32_t* d = reinterpret_cast<uint32_t*>(&dst);
     const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
     for (int i = threadIdx.x; i < int(sizeof(BondTable) / 4); i += kBlock) d[i] = *gptr(w + i);
+}
+
+template <typename L, int MODE, typename T, int VB>
+__global__ __launch_bounds__(kBlock) void hv_kernel(SectorDev S, BondTable B, HvLaunch h) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ BondTable Bs;
+    stage_bonds(Bs, &B);
+    const HvLds lds = hv_lds_setup<MODE>(smem, S);
+    __syncthreads();
+    hv_body<L, MODE, T, VB, kEpiPlain>(S, Bs, lds, static_cast<const T*>(h.x), static_cast<T*>(h.y), h.ld, h.col0,
+                                        h.row0, h.nrows, blockIdx.x, gridDim.x, nullptr, false, nullptr);
 }
 
 // The epilogue scalars [hv_a | hv_b] of columns [col0, col0 + VB), in the
@@ -470,9 +474,18 @@ __global__ __launch_bounds__(kBlock) void hv_split_lanczos_kernel(LanczosLaunch 
     alpha_tail<VB>(sw, a, wsum, lds.red, local, &flag);
 }
 
+// Dynamic LDS of the plain H.x at 20 and more FP32 columns: enough that two
+// workgroups fill a CU's 160 KB. Registers would allow six; with more rows in
+// flight the partner rows are evicted before their reuse (at N = 30, 20
+// columns: 74 -> 69 ms with CLT, 63 -> 58 ms with CR; 32 columns: 218 -> 187
+// ms with CLT). Narrower blocks keep the register-limited occupancy.
+template <typename T, int VB>
+constexpr size_t hv_plain_lds_floor() { return (sizeof(T) == 4 && VB >= 20) ? size_t(72) * 1024 : 0; }
+
 template <typename L, int MODE, typename T, int VB>
 hipError_t launch_hv_one(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st) {
-    const size_t lds = hv_lds_bytes(s);
+    const size_t need = hv_lds_bytes(s), floor = hv_plain_lds_floor<T, VB>();
+    const size_t lds = need > floor ? need : floor;
     auto kern = hv_kernel<L, MODE, T, VB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
