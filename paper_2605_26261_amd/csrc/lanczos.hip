@@ -149,7 +149,14 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
     const uint32_t dim = sw.S.dim;
     const T* __restrict__ u = static_cast<const T*>(sw.u[(step - 1) & 1]);
     T* __restrict__ w = static_cast<T*>(sw.u[step & 1]);
-    const Chain* chains = sw.chains + a.col0;
+    // the update coefficients, read once (through a generic pointer the
+    // compiler would re-read them after every store of the tile loop)
+    T coef[VB];
+#pragma unroll
+    for (int c = 0; c < VB; ++c) {
+        const Chain* ch = sw.chains + a.col0 + c;
+        coef[c] = sizeof(T) == 4 ? T(ch->up_f) : T(ch->up_d);
+    }
     double part[VB];
 #pragma unroll
     for (int c = 0; c < VB; ++c) part[c] = 0.0;
@@ -163,10 +170,11 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
                 const uint32_t t0 = tile * kBlock;
                 const uint32_t rows = dim - t0 < uint32_t(kBlock) ? dim - t0 : uint32_t(kBlock);
                 const uint32_t n16 = rows * uint32_t(VB * sizeof(T)) / 16u;
-                const float4* gu = reinterpret_cast<const float4*>(u + uint64_t(t0) * VB);
-                float4* gw = reinterpret_cast<float4*>(w + uint64_t(t0) * VB);
-                float4* lu = reinterpret_cast<float4*>(stage_u);
-                float4* lw = reinterpret_cast<float4*>(stage_w);
+                using V16 = uint32_t __attribute__((ext_vector_type(4)));  // 16 bytes
+                const V16 FTLM_GLOBAL* gu = gptr(reinterpret_cast<const V16*>(u + uint64_t(t0) * VB));
+                V16 FTLM_GLOBAL* gw = gptr(reinterpret_cast<V16*>(w + uint64_t(t0) * VB));
+                V16* lu = reinterpret_cast<V16*>(stage_u);
+                V16* lw = reinterpret_cast<V16*>(stage_w);
                 for (uint32_t i = threadIdx.x; i < n16; i += kBlock) {
                     lu[i] = gu[i];
                     lw[i] = gw[i];
@@ -177,8 +185,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
                     const T* ur = stage_u + threadIdx.x * VB;
 #pragma unroll
                     for (int c = 0; c < VB; ++c) {
-                        const T coef = sizeof(T) == 4 ? T(chains[c].up_f) : T(chains[c].up_d);
-                        const T v = wr[c] - coef * ur[c];
+                        const T v = wr[c] - coef[c] * ur[c];
                         part[c] += double(v) * double(v);
                         wr[c] = v;
                     }
@@ -196,8 +203,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
         load_row<T, VB>(wrow, ww);
 #pragma unroll
         for (int c = 0; c < VB; ++c) {
-            const T coef = sizeof(T) == 4 ? T(chains[c].up_f) : T(chains[c].up_d);
-            ww[c] = ww[c] - coef * uu[c];
+            ww[c] = ww[c] - coef[c] * uu[c];
             part[c] += double(ww[c]) * double(ww[c]);
         }
         store_row<T, VB>(wrow, ww);
