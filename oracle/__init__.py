@@ -17,7 +17,7 @@ paper's algorithm step by step in FP64:
 * Boltzmann sums Eqs. (4)-(8) per S^z sector, C = beta^2 Var(H), and the
   susceptibility of Eq. (9).
 
-Readings of points the paper leaves open (each listed in the design doc):
+Readings of points the paper leaves open:
 * the order of operations in a Lanczos step (Paige's ordering: w = Hq -
   beta_{k-1} q_{k-1}, alpha = <q, w>, w -= alpha q, beta = |w|);
 * the stopping rule: k = min(M, D), or beta_k <= eps * max_{j<=k}(|alpha_j|,
