@@ -167,7 +167,7 @@ __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, 
                                         uint32_t col0, uint32_t row0, uint32_t nrows, uint32_t bid,
                                         uint32_t G, const T* ab, bool first, double* wsum) {
     const Binom C{lds.binom, S.bw};
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
     const T jsum4 = sizeof(T) == 4 ? T(B.jsum4_f) : T(B.jsum4_d);
     const uint32_t ntiles = (nrows + kBlock - 1) / kBlock;
     for_each_tile(ntiles, bid, G, [&](uint32_t tile) {
@@ -203,14 +203,11 @@ __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, 
             store_row<T, VB>(yrow, out);
         }
         if constexpr (EPI == kEpiLanczos) {
-            // every lane takes part in the butterfly; rows past the end add 0
+            // every lane takes part; rows past the end add 0
+            double p[VB];
 #pragma unroll
-            for (int c = 0; c < VB; ++c) {
-                double p = valid ? double(xt[c]) * double(out[c]) : 0.0;
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off, 64);
-                if (lane == 0) wsum[wave * VB + c] += p;
-            }
+            for (int c = 0; c < VB; ++c) p[c] = valid ? double(xt[c]) * double(out[c]) : 0.0;
+            wave_fold_columns<VB>(p, wsum + wave * VB);
         }
     });
 }
@@ -388,7 +385,7 @@ __device__ __forceinline__ void hv_split_body(const SectorDev& S, const BondTabl
                                               uint32_t col0, uint32_t bid, uint32_t G, const T* ab,
                                               double* wsum) {
     const Binom C{lds.binom, S.bw};
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
     const SplitSched sc(c, s, S.n_sites, S.n_up, C);
     const uint32_t xcd = bid & 7u, slot = bid >> 3, per = G >> 3;
     const uint32_t total = sc.walk(xcd, 0, nullptr);
@@ -425,13 +422,10 @@ __device__ __forceinline__ void hv_split_body(const SectorDev& S, const BondTabl
             store_row<T, VB>(yrow, out);
         }
         if constexpr (EPI == kEpiLanczos) {
+            double p[VB];
 #pragma unroll
-            for (int i = 0; i < VB; ++i) {
-                double p = valid ? double(xt[i]) * double(out[i]) : 0.0;
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off, 64);
-                if (lane == 0) wsum[wave * VB + i] += p;
-            }
+            for (int i = 0; i < VB; ++i) p[i] = valid ? double(xt[i]) * double(out[i]) : 0.0;
+            wave_fold_columns<VB>(p, wsum + wave * VB);
         }
     }
 }

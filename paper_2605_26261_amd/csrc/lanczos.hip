@@ -122,15 +122,23 @@ __global__ __launch_bounds__(kBlock) void start_kernel(LanczosLaunch a) {
 // stopping rule: a chain stops after step k when k reaches min(M, D) or
 // beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}). A stopped chain gets
 // zero scales, so its columns stay zero in every later step.
-// Blocks whose rows are 48 to 96 bytes (a multiple of 16) go through LDS a
-// tile at a time: the tile's rows of u and w are contiguous, so they move with
-// fully coalesced 16-byte accesses, while each thread still updates its own
-// row (the same arithmetic and summation order as without the staging). With
-// one thread per row, a 16-byte access of rows that wide spans several cache
-// lines per wave; narrower rows are already well coalesced.
+// Blocks whose rows are 48 to 128 bytes (a multiple of 16) go through LDS:
+// the rows of u and w staged together are contiguous, so they move with fully
+// coalesced 16-byte accesses, while each thread still updates its own row (the
+// same arithmetic and summation order as without the staging). With one
+// thread per row, a 16-byte access of rows that wide spans several cache lines
+// per wave; narrower rows are already well coalesced. Rows of up to 96 bytes
+// are staged a whole tile at a time, 128-byte rows half a tile at a time (two
+// 256-row tiles would not fit the static LDS); without the staging, 128-byte
+// rows ran at under 1 TB/s.
 template <typename T, int VB>
 __host__ __device__ constexpr bool update_staged() {
-    return (VB * sizeof(T)) % 16 == 0 && VB * sizeof(T) >= 48 && VB * sizeof(T) <= 96;
+    return (VB * sizeof(T)) % 16 == 0 && VB * sizeof(T) >= 48 && VB * sizeof(T) <= 128;
+}
+
+template <typename T, int VB>
+__host__ __device__ constexpr int update_stage_rows() {
+    return VB * sizeof(T) <= 96 ? kBlock : kBlock / 2;
 }
 
 template <typename T, int VB>
@@ -138,8 +146,9 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
     __shared__ double red[kBlock];
     __shared__ int flag;
     constexpr bool kStage = update_staged<T, VB>();
-    __shared__ __align__(16) T stage_u[kStage ? kBlock * VB : 1];
-    __shared__ __align__(16) T stage_w[kStage ? kBlock * VB : 1];
+    constexpr int kStageRows = update_stage_rows<T, VB>();
+    __shared__ __align__(16) T stage_u[kStage ? kStageRows * VB : 1];
+    __shared__ __align__(16) T stage_w[kStage ? kStageRows * VB : 1];
     uint32_t local = 0;
     const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
     if (s < 0) return;
@@ -169,30 +178,35 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
             if (staged) {
                 const uint32_t t0 = tile * kBlock;
                 const uint32_t rows = dim - t0 < uint32_t(kBlock) ? dim - t0 : uint32_t(kBlock);
-                const uint32_t n16 = rows * uint32_t(VB * sizeof(T)) / 16u;
                 using V16 = uint32_t __attribute__((ext_vector_type(4)));  // 16 bytes
-                const V16 FTLM_GLOBAL* gu = gptr(reinterpret_cast<const V16*>(u + uint64_t(t0) * VB));
-                V16 FTLM_GLOBAL* gw = gptr(reinterpret_cast<V16*>(w + uint64_t(t0) * VB));
                 V16* lu = reinterpret_cast<V16*>(stage_u);
                 V16* lw = reinterpret_cast<V16*>(stage_w);
-                for (uint32_t i = threadIdx.x; i < n16; i += kBlock) {
-                    lu[i] = gu[i];
-                    lw[i] = gw[i];
-                }
-                __syncthreads();
-                if (threadIdx.x < rows) {
-                    T* wr = stage_w + threadIdx.x * VB;
-                    const T* ur = stage_u + threadIdx.x * VB;
-#pragma unroll
-                    for (int c = 0; c < VB; ++c) {
-                        const T v = wr[c] - coef[c] * ur[c];
-                        part[c] += double(v) * double(v);
-                        wr[c] = v;
+                // rows [h0, h0 + hr) of the tile at a time (block-uniform bounds)
+                for (uint32_t h0 = 0; h0 < rows; h0 += uint32_t(kStageRows)) {
+                    const uint32_t hr = rows - h0 < uint32_t(kStageRows) ? rows - h0 : uint32_t(kStageRows);
+                    const uint32_t n16 = hr * uint32_t(VB * sizeof(T)) / 16u;
+                    const V16 FTLM_GLOBAL* gu = gptr(reinterpret_cast<const V16*>(u + uint64_t(t0 + h0) * VB));
+                    V16 FTLM_GLOBAL* gw = gptr(reinterpret_cast<V16*>(w + uint64_t(t0 + h0) * VB));
+                    for (uint32_t i = threadIdx.x; i < n16; i += kBlock) {
+                        lu[i] = gu[i];
+                        lw[i] = gw[i];
                     }
+                    __syncthreads();
+                    // each thread updates the row it owns (row threadIdx.x of the tile)
+                    if (threadIdx.x >= h0 && threadIdx.x < h0 + hr) {
+                        T* wr = stage_w + (threadIdx.x - h0) * VB;
+                        const T* ur = stage_u + (threadIdx.x - h0) * VB;
+#pragma unroll
+                        for (int c = 0; c < VB; ++c) {
+                            const T v = wr[c] - coef[c] * ur[c];
+                            part[c] += double(v) * double(v);
+                            wr[c] = v;
+                        }
+                    }
+                    __syncthreads();
+                    for (uint32_t i = threadIdx.x; i < n16; i += kBlock) gw[i] = lw[i];
+                    __syncthreads();
                 }
-                __syncthreads();
-                for (uint32_t i = threadIdx.x; i < n16; i += kBlock) gw[i] = lw[i];
-                __syncthreads();
                 return;
             }
         }

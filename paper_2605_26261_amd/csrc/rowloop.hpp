@@ -24,6 +24,53 @@ __device__ __forceinline__ void for_each_tile(uint32_t ntiles, uint32_t bid, uin
     }
 }
 
+// One level of wave_fold_columns: lanes l and l ^ off hold partial sums of
+// the same columns [lo, hi) in slots [0, SK); the lane with bit `off` clear
+// keeps [lo, lo + SN), the other keeps [lo + SN, hi), and each adds the
+// partner's partial sum of the columns it keeps to its own (own + partner,
+// the order of the xor butterfly). Slots past a lane's columns carry no
+// column and are never stored.
+template <int SK, int SN, int VB>
+__device__ __forceinline__ void fold_level(double (&v)[VB], int off, int lane, int& lo, int& hi) {
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+        const double keep_lo = v[j];
+        const double keep_hi = (SN + j < SK) ? v[SN + j] : 0.0;
+        const double recv = __shfl_xor(up ? keep_lo : keep_hi, off, 64);
+        v[j] = (up ? keep_hi : keep_lo) + recv;
+    }
+    const int mid = lo + SN;
+    if (up) lo = mid;
+    else hi = hi < mid ? hi : mid;
+}
+
+// Adds the sums over a wave's 64 lanes of p[0..VB) to dst[0..VB) (LDS). Each
+// column's sum is the one of the xor butterfly over lane offsets 32, 16, ...,
+// 1: the same pairs of partial sums are added, in the same order, at every
+// level. The columns are reduced by recursive halving, though: at each level
+// a lane keeps half of its columns, so VB columns take about VB + 6 exchanges
+// instead of 6 VB, and column c ends in the one lane that stores it. Called by
+// whole waves; VB <= 64.
+template <int VB>
+__device__ __forceinline__ void wave_fold_columns(const double (&p)[VB], double* dst) {
+    constexpr int S1 = (VB + 1) / 2, S2 = (S1 + 1) / 2, S3 = (S2 + 1) / 2;
+    constexpr int S4 = (S3 + 1) / 2, S5 = (S4 + 1) / 2, S6 = (S5 + 1) / 2;
+    static_assert(S6 == 1, "at most 64 columns");
+    const int lane = threadIdx.x & 63;
+    double v[VB];
+#pragma unroll
+    for (int c = 0; c < VB; ++c) v[c] = p[c];
+    int lo = 0, hi = VB;
+    fold_level<VB, S1>(v, 32, lane, lo, hi);
+    fold_level<S1, S2>(v, 16, lane, lo, hi);
+    fold_level<S2, S3>(v, 8, lane, lo, hi);
+    fold_level<S3, S4>(v, 4, lane, lo, hi);
+    fold_level<S4, S5>(v, 2, lane, lo, hi);
+    fold_level<S5, S6>(v, 1, lane, lo, hi);
+    if (lo < hi) dst[lo] += v[0];
+}
+
 // Sums v[0..N) over the workgroup in a fixed order (butterfly inside each
 // wave, then the waves in order). red must hold (kWaves + 1) * N doubles;
 // after the call red[kWaves * N + c] holds the block total of column c,
