@@ -188,8 +188,9 @@ def run_gpu(args):
 def plan_vs_plain():
     """The batched all-sector workload (6x4 J1-J2 lattice, 13 sectors, R = 32
     +-1 chains per sector, M = 80): one hipGraph-captured plan (one launch per
-    kernel per step over all sectors) against the plain form (one sector and
-    one chain at a time, eager). FTLM samples/s each."""
+    kernel per step over all sectors, its column split chosen by
+    ftlm_plan_tune) against the plain form (one sector and one chain at a
+    time, eager). FTLM samples/s each."""
     import numpy as np
     import torch
 
@@ -201,6 +202,7 @@ def plan_vs_plain():
     g = ftlm.Graph(n, bonds)
     n_ups = list(range(12, 25))
     plan = ftlm.Plan(g, n_ups, ftlm.CR, R, M, ftlm.F32)
+    tuning = plan.tune()  # split of the 32 columns into launches
     plan.run(seed, ftlm.PM1, use_graph=True)  # capture + warm up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -223,6 +225,8 @@ def plan_vs_plain():
     samples = R * len(n_ups)
     return {"workload": "6x4 J1-J2 lattice (N=24, J2=0.5), all 13 sectors, R=32 +-1, M=80, FP32",
             "plan_graph_s": t_plan, "plan_samples_per_s": samples / t_plan,
+            "plan_max_width": tuning["max_width"],
+            "plan_tuning_ms": {str(w): round(ms, 3) for w, (_, ms) in tuning["candidates"].items()},
             "plain_s_estimated": t_plain, "plain_samples_per_s": samples / t_plain,
             "plain_protocol": f"one chain per launch, sector by sector, eager; {per} of {R} chains per sector timed"}
 
@@ -395,9 +399,16 @@ def main():
     ap.add_argument("--batch", default="auto", help="chains per Lanczos batch ('auto': the autotuner's choice)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short kernel-only run for rocprofv3 counter passes")
+    ap.add_argument("--only", choices=["plan", "serving", "largest"],
+                    help="run one secondary measurement alone and print its JSON (for kernel traces)")
     args = ap.parse_args()
     if args.profile_kernels:
         profile_kernels(R if args.batch == "auto" else int(args.batch))
+        return
+    if args.only:
+        run = {"plan": plan_vs_plain, "largest": largest_sector,
+               "serving": lambda: serving(n_meas=args.serve_requests)}[args.only]
+        print(json.dumps({args.only: run()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (use --gpus 1)",

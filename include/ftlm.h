@@ -288,6 +288,28 @@ int ftlm_plan_create(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, i
  * the work already enqueued on `stream`. */
 int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_graph, double* alpha_host,
                   double* beta_host, int32_t* steps_host, void* stream);
+
+/* ftlm_plan_tune: chooses how the plan's R columns are split into kernel
+ * launches (the vector-block widths of the batched Lanczos step, Sec. 3.4).
+ * Candidates are the widest-first splits into launches of at most 32, 20,
+ * 16, 8 and 4 columns (FP64: 16, 8, 4), distinct ones only; each is timed
+ * over one Lanczos step of the whole plan, after a warm-up step, with HIP
+ * events on the plan's stream (ordered after the work on `stream`), twice,
+ * keeping the faster time. The fastest candidate is kept for later
+ * ftlm_plan_run calls; a graph captured before is dropped and captured again
+ * by the next run with use_graph != 0. Chains are bitwise the same under
+ * every split (the reduction order depends only on each sector's D). The
+ * plan's vector blocks are overwritten. out may be NULL. Synchronizes.
+ * Errors: FTLM_E_INVALID for a null plan, FTLM_E_DEVICE for a HIP error (the
+ * plan then keeps its previous split). */
+typedef struct ftlm_plan_tuning {
+    int32_t n_candidates;
+    int32_t chosen;          /* index of the kept candidate */
+    int32_t max_width[8];    /* widest launch allowed in candidate i */
+    int32_t n_launches[8];   /* kernel launches per Lanczos step of candidate i */
+    double ms[8];            /* measured milliseconds of one Lanczos step */
+} ftlm_plan_tuning;
+int ftlm_plan_tune(ftlm_plan* p, void* stream, ftlm_plan_tuning* out);
 void ftlm_plan_destroy(ftlm_plan* p);
 
 /* ---- request server (continuous batching) ----------------------------------

@@ -601,6 +601,69 @@ int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_gr
     return ok();
 }
 
+int ftlm_plan_tune(ftlm_plan* p, void* stream, ftlm_plan_tuning* out) {
+    if (!p) return fail(FTLM_E_INVALID, "null argument");
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    HIP_CHECK(hipEventCreate(&ev.e0));
+    HIP_CHECK(hipEventCreate(&ev.e1));
+    HIP_CHECK(hipEventRecord(p->ready, static_cast<hipStream_t>(stream)));
+    HIP_CHECK(hipStreamWaitEvent(p->stream, p->ready, 0));
+    static const int caps32[] = {32, 20, 16, 8, 4}, caps64[] = {16, 8, 4};
+    const int* caps = p->dtype == FTLM_F32 ? caps32 : caps64;
+    const int ncap = p->dtype == FTLM_F32 ? 5 : 3;
+    const auto previous = p->job.chunks;
+    std::vector<std::vector<std::pair<int, int>>> seen;
+    ftlm_plan_tuning t{};
+    double best = 1e300;
+    for (int i = 0; i < ncap; ++i) {
+        auto chunks = job_chunks(p->job, caps[i]);
+        if (std::find(seen.begin(), seen.end(), chunks) != seen.end()) continue;
+        seen.push_back(chunks);
+        p->job.chunks = chunks;
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            int rc = job_start(p->job, 0, 0, FTLM_PM1, p->stream);
+            if (rc == FTLM_OK) rc = job_steps(p->job, p->stream, false, 1);
+            if (rc == FTLM_OK && hipEventRecord(ev.e0, p->stream) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc == FTLM_OK) rc = job_steps(p->job, p->stream, false, 1);
+            if (rc == FTLM_OK && hipEventRecord(ev.e1, p->stream) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc == FTLM_OK && hipEventSynchronize(ev.e1) != hipSuccess) rc = FTLM_E_DEVICE;
+            float ms = 0.f;
+            if (rc == FTLM_OK && hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc != FTLM_OK) {
+                p->job.chunks = previous;
+                return rc == FTLM_E_DEVICE ? fail(rc, "plan tuning: HIP error") : rc;
+            }
+            best_ms = std::min(best_ms, ms);
+        }
+        const int n = t.n_candidates++;
+        t.max_width[n] = caps[i];
+        t.n_launches[n] = int32_t(chunks.size());
+        t.ms[n] = best_ms;
+        if (best_ms < best) {
+            best = best_ms;
+            t.chosen = n;
+        }
+    }
+    p->job.chunks = seen[size_t(t.chosen)];
+    if (p->exec) {
+        (void)hipGraphExecDestroy(p->exec);
+        p->exec = nullptr;
+    }
+    if (p->graph) {
+        (void)hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    if (out) *out = t;
+    return ok();
+}
+
 void ftlm_plan_destroy(ftlm_plan* p) {
     if (p && p->stream) (void)hipStreamSynchronize(p->stream);
     delete p;

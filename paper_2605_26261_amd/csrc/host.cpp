@@ -56,9 +56,11 @@ uint64_t stream_key(uint64_t seed, int n_up, uint64_t r) {
 Stats g_stats;
 
 // ---- column chunking of a [D][ld] block --------------------------------------
-// Splits columns [0, nvec) into kernel widths, widest first, keeping every
-// vector access naturally aligned (ld, col0 and the base pointers).
-std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtype, const std::vector<const void*>& ptrs) {
+// Splits columns [0, nvec) into kernel widths of at most max_width, widest
+// first, keeping every vector access naturally aligned (ld, col0 and the base
+// pointers).
+std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtype, const std::vector<const void*>& ptrs,
+                                                 int max_width) {
     const size_t es = dtype == FTLM_F32 ? 4 : 8;
     static const int w32[] = {32, 20, 16, 8, 4, 2, 1};
     static const int w64[] = {16, 8, 4, 2, 1};
@@ -69,7 +71,7 @@ std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtyp
     while (col < nvec) {
         for (int i = 0; i < nw; ++i) {
             const int vb = widths[i];
-            if (vb > nvec - col) continue;
+            if (vb > nvec - col || (vb > max_width && vb > 1)) continue;
             size_t vbytes = es;
             if (es == 4 && vb % 4 == 0) vbytes = 16;
             else if (vb % 2 == 0) vbytes = 2 * es;
@@ -87,6 +89,15 @@ std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtyp
 std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype,
                                                std::initializer_list<const void*> ptrs) {
     return column_chunks_v(nvec, ld, dtype, std::vector<const void*>(ptrs));
+}
+
+std::vector<std::pair<int, int>> job_chunks(const LanczosJob& job, int max_width) {
+    std::vector<const void*> ptrs;
+    for (const auto& w : job.secs) {
+        ptrs.push_back(w.u[0]);
+        ptrs.push_back(w.u[1]);
+    }
+    return column_chunks_v(job.R, uint64_t(job.R), job.dtype, ptrs, max_width);
 }
 
 int check_dtype(int dtype) {
@@ -183,12 +194,7 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
     }
     job.grid = int(block);
     job.lds = lds;
-    std::vector<const void*> ptrs;
-    for (auto& w : job.secs) {
-        ptrs.push_back(w.u[0]);
-        ptrs.push_back(w.u[1]);
-    }
-    job.chunks = column_chunks_v(R, uint64_t(R), dtype, ptrs);
+    job.chunks = job_chunks(job, 32);
 }
 
 // Start vectors of samples r0 .. r0 + R - 1 in every sector of the job.

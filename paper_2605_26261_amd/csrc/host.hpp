@@ -93,7 +93,8 @@ struct HvTimer {
     }
 };
 
-std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtype, const std::vector<const void*>& ptrs);
+std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtype, const std::vector<const void*>& ptrs,
+                                                 int max_width = 32);
 std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype, std::initializer_list<const void*> ptrs);
 int check_dtype(int dtype);
 
@@ -143,6 +144,8 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
                 void* base, int R, int M, int dtype, SecWork* dev_secs, const std::vector<const ftlm_graph*>& graphs,
                 const std::vector<BondTable*>& dev_tables, const std::vector<int>& graph_of);
 int job_start(LanczosJob& job, uint64_t seed, uint64_t r0, int dist, hipStream_t st);
+// The job's columns split into launches of at most max_width columns.
+std::vector<std::pair<int, int>> job_chunks(const LanczosJob& job, int max_width);
 int job_steps(const LanczosJob& job, hipStream_t st, bool timed = true, int nsteps = -1);
 int job_collect(const LanczosJob& job, int M, double* alpha_host, double* beta_host, int32_t* steps_host,
                 hipStream_t st);

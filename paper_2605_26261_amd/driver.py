@@ -71,10 +71,14 @@ def plan_records(plan, n_sites, seed, dist, r0=0, use_graph=True):
 
 
 def run_plan(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, temps=None, g=1.0,
-             use_graph=True, device="cuda"):
-    """Full FTLM over the listed sectors as one batched plan."""
+             use_graph=True, device="cuda", tune=True):
+    """Full FTLM over the listed sectors as one batched plan (its split of the
+    R columns into launches timed and chosen by ftlm_plan_tune unless
+    tune=False; the chains do not depend on it)."""
     temps = log_temperatures() if temps is None else temps
     graph = ftlm.Graph(n_sites, bonds)
     plan = ftlm.Plan(graph, n_ups, mode, R, M, dtype, device=device)
+    if tune:
+        plan.tune()
     recs = plan_records(plan, n_sites, seed, dist, use_graph=use_graph)
     return ftlm.thermo(n_sites, recs, temps, g), recs

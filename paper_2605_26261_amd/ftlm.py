@@ -70,6 +70,7 @@ _sig("ftlm_lanczos", _i32, [_vp, _vp, _u64, _u64, _i32, _i32, _i32, _i32, _vp, _
 _sig("ftlm_plan_workspace_bytes", _i32, [_vp, _i32, _vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("ftlm_plan_create", _i32, [_vp, _i32, _vp, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)])
 _sig("ftlm_plan_run", _i32, [_vp, _u64, _u64, _i32, _i32, _vp, _vp, _vp, _vp])
+_sig("ftlm_plan_tune", _i32, [_vp, _vp, _vp])
 _sig("ftlm_plan_destroy", None, [_vp])
 _sig("ftlm_ritz", _i32, [_i32, _vp, _vp, _vp, _vp])
 _sig("ftlm_thermo", _i32, [_i32, _i32, ctypes.POINTER(SectorResult), _i32, _vp, _dbl, _vp, _vp, _vp, _vp])
@@ -85,6 +86,13 @@ class Tuning(ctypes.Structure):
 
 
 _sig("ftlm_autotune", _i32, [_vp, _vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(Tuning)])
+
+
+class PlanTuning(ctypes.Structure):
+    """ftlm_plan_tuning."""
+    _fields_ = [("n_candidates", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("max_width", ctypes.c_int32 * 8), ("n_launches", ctypes.c_int32 * 8),
+                ("ms", ctypes.c_double * 8)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -329,6 +337,15 @@ class Plan:
         _check(_lib.ftlm_plan_run(self.handle, seed, r0, dist, 1 if use_graph else 0, _hptr(alpha), _hptr(beta),
                                   _hptr(steps), _stream(stream)))
         return alpha, beta, steps
+
+    def tune(self, stream=None):
+        """ftlm_plan_tune: keeps the fastest split of the R columns into
+        launches; returns the candidates {max_width: (launches, ms)} and the
+        chosen max_width."""
+        t = PlanTuning()
+        _check(_lib.ftlm_plan_tune(self.handle, _stream(stream), ctypes.byref(t)))
+        cands = {int(t.max_width[i]): (int(t.n_launches[i]), float(t.ms[i])) for i in range(t.n_candidates)}
+        return {"candidates": cands, "max_width": int(t.max_width[t.chosen])}
 
     def __del__(self):
         if getattr(self, "handle", None):

@@ -146,3 +146,34 @@ def test_square4x6_all_sectors_against_reference(env):
     th = ftlm.thermo(n, recs, np.array(ref["temps"]), 1.0)
     for key in ("E", "C", "chi"):
         _close_obs(th[key], np.array(ref[key]))
+
+
+@pytest.mark.parametrize("dtype,R", [(0, 32), (0, 20), (1, 16)])
+def test_plan_tune_keeps_every_chain(env, dtype, R):
+    # the tuned split of the columns into launches changes no chain: eager
+    # and graph runs after tuning equal the untuned run bit for bit
+    torch, ftlm, driver = env
+    n = 16
+    g = ftlm.Graph(n, graphs.square_j1j2(4, 4, 1.0, 0.5))
+    n_ups = list(range(8, 17))
+    M = 30
+    plan = ftlm.Plan(g, n_ups, ftlm.CR, R, M, dtype)
+    a0, b0, s0 = plan.run(9, ftlm.PM1, use_graph=True)
+    t = plan.tune()
+    cands = t["candidates"]
+    assert t["max_width"] in cands and len(cands) >= 2
+    assert all(ms > 0 and launches >= 1 for launches, ms in cands.values())
+    # the widest split is one launch when R is a kernel width; a cap of 4 gives ceil(R / 4)
+    assert cands[max(cands)][0] == 1 and cands[4][0] == (R + 3) // 4
+    for use_graph in (True, True, False):
+        a, b, s = plan.run(9, ftlm.PM1, use_graph=use_graph)
+        np.testing.assert_array_equal(s, s0)
+        np.testing.assert_array_equal(a, a0)
+        np.testing.assert_array_equal(b, b0)
+    # tuning again (the graph is dropped and captured again) changes nothing
+    t2 = plan.tune()
+    assert set(t2["candidates"]) == set(cands)
+    a, b, s = plan.run(9, ftlm.PM1, use_graph=True)
+    np.testing.assert_array_equal(a, a0)
+    np.testing.assert_array_equal(b, b0)
+    del plan
