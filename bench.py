@@ -231,7 +231,7 @@ def plan_vs_plain():
             "plain_protocol": f"one chain per launch, sector by sector, eager; {per} of {R} chains per sector timed"}
 
 
-def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True):
+def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True, steps_per_round=0):
     """Poisson-arriving exchange-fit requests (N in 16..28, random clusters,
     J in [0.2, 1.5], one random sector, R = 16, M = 80) through the
     continuous-batching server; p50/p99 latency (arrival to result) and
@@ -245,7 +245,7 @@ def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True):
 
     reqs = exchange_fit_stream(n_warm + n_meas, seed=4, rate=rate)
     temps = driver.log_temperatures()
-    srv = ftlm.Server(48 << 30, mode=ftlm.CR, dtype=ftlm.F32, max_active=max_active)
+    srv = ftlm.Server(48 << 30, mode=ftlm.CR, dtype=ftlm.F32, max_active=max_active, steps_per_round=steps_per_round)
     t0 = srv.clock()
     pending, done, k = {}, {}, 0
     while len(done) < len(reqs):
@@ -267,7 +267,7 @@ def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True):
     served_sps = 16 * len(meas) / span
     out = {"workload": f"Poisson {rate:g}/s exchange-fit stream, N in 16..28, R=16, M=80, FP32; "
                        f"{n_warm} warm-up + {n_meas} measured requests",
-           "max_active": max_active or 16,
+           "max_active": max_active or 16, "steps_per_round": steps_per_round or 4,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "samples_per_s": served_sps, "peak_arena_bytes": stats["peak_bytes"], "rounds": stats["rounds"]}
     if not plain:

@@ -333,6 +333,10 @@ typedef struct ftlm_server_opts {
                               finishes the oldest requests first at the same throughput, since
                               every round still fills the device) */
     int32_t batch_same_n;  /* 1: one launch per step for all active requests of equal N and R */
+    int32_t steps_per_round;  /* Lanczos steps issued per round before finished requests are
+                                 looked for, 1..64 (0 = 4); a request that finishes inside a
+                                 round costs its remaining steps of the round one early return
+                                 per block */
 } ftlm_server_opts;
 
 /* One FTLM job: R chains of M Lanczos steps in the sector n_up of the graph,

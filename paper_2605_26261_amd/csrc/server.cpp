@@ -5,11 +5,13 @@
 // launch group); the rest is handed out first fit, one block per request:
 // its SecWork slot, bond table, sector tables and Lanczos state. Each round
 // the worker admits waiting requests in arrival order while they fit, then
-// issues one Lanczos step (H.x with fused alpha, update with fused beta) per
-// group of active requests with equal N and R, reads back every active
-// request's count of running chains, and retires the finished ones: their
-// alpha/beta come back to the host, the Ritz values and the thermal
-// reduction run there, and their memory returns to the arena.
+// issues steps_per_round Lanczos steps (H.x with fused alpha, update with
+// fused beta) per group of active requests with equal N and R, reads back
+// every active request's count of running chains (one synchronization per
+// round), and retires the finished ones: their alpha/beta come back to the
+// host, the Ritz values and the thermal reduction run there, and their memory
+// returns to the arena. Chains that stop inside a round leave their sector's
+// later launches of the round an early return per block.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -30,6 +32,8 @@ namespace {
 
 constexpr int kServerMaxActive = 256;
 constexpr int kServerDefaultActive = 16;
+constexpr int kServerMaxSteps = 64;
+constexpr int kServerDefaultSteps = 4;
 
 struct Request {
     uint64_t id = 0;
@@ -149,6 +153,9 @@ struct ftlm_server {
     // worker-only state
     Arena heap;
     std::vector<std::shared_ptr<Request>> active;
+    SecWork* desc_host = nullptr;          // pinned staging of the round's descriptors
+    int32_t* state_host = nullptr;         // pinned [kServerMaxActive][2] readback
+    std::vector<uint64_t> desc_ids;        // active requests whose descriptors are on the device
     int fatal = FTLM_OK;
     // monitoring values published by the worker
     std::atomic<uint64_t> rounds{0}, peak{0};
@@ -221,16 +228,20 @@ void ftlm_server::retire(const std::shared_ptr<Request>& r) {
     r->t_done = now();
 }
 
-// One Lanczos step for every active request: one launch pair per group of
-// equal (N, R), or per request when batch_same_n is off.
+// steps_per_round Lanczos steps for every active request: one launch pair
+// per step per group of equal (N, R), or per request when batch_same_n is
+// off. The groups' descriptor arrays go to the device only when the active
+// set has changed since the last round.
 int ftlm_server::round() {
     std::map<std::pair<int, int>, std::vector<Request*>> groups;
+    std::vector<uint64_t> ids;
     for (auto& r : active) {
         const std::pair<int, int> key = opts.batch_same_n ? std::make_pair(r->n_sites, r->R)
                                                           : std::make_pair(int(r->id), -1);
         groups[key].push_back(r.get());
     }
     SecWork* desc = reinterpret_cast<SecWork*>(arena);
+    std::vector<LanczosJob> jobs;
     size_t slot = 0;
     for (auto& [key, reqs] : groups) {
         // the group's descriptor array: each member's SecWork, blocks re-based
@@ -245,28 +256,35 @@ int ftlm_server::round() {
             SecWork w = r->job.secs[0];
             w.block0 = block;
             block = (block + w.G + 7) & ~7u;
+            desc_host[slot + g.secs.size()] = w;
             g.secs.push_back(w);
             g.lds = std::max(g.lds, r->job.lds);
             g.any_split = g.any_split || r->job.any_split;
+            ids.push_back(r->id);
         }
         g.grid = int(block);
         // equal R and 256-byte aligned blocks give every member the same chunks
         g.chunks = reqs[0]->job.chunks;
         g.dev_secs = desc + slot;
         slot += reqs.size();
-        HIP_CHECK(hipMemcpyAsync(g.dev_secs, g.secs.data(), g.secs.size() * sizeof(SecWork), hipMemcpyHostToDevice,
-                                 stream));
-        if (int rc = job_steps(g, stream, true, 1)) return rc;
-        // keep the host copies alive until the copy has been consumed
-        HIP_CHECK(hipStreamSynchronize(stream));
+        jobs.push_back(std::move(g));
     }
+    // the pinned staging is rewritten only after the previous round's
+    // synchronization, so the copy below never races a pending one
+    if (ids != desc_ids) {
+        HIP_CHECK(hipMemcpyAsync(desc, desc_host, slot * sizeof(SecWork), hipMemcpyHostToDevice, stream));
+        desc_ids = ids;
+    }
+    const int nsteps = opts.steps_per_round > 0 ? opts.steps_per_round : kServerDefaultSteps;
+    for (int k = 0; k < nsteps; ++k)
+        for (const LanczosJob& g : jobs)
+            if (int rc = job_steps(g, stream, true, 1)) return rc;
     // read back every active request's count of running chains
-    std::vector<int32_t> st(active.size() * 2);
     for (size_t i = 0; i < active.size(); ++i)
-        HIP_CHECK(hipMemcpyAsync(&st[2 * i], active[i]->job.secs[0].state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                 stream));
+        HIP_CHECK(hipMemcpyAsync(&state_host[2 * i], active[i]->job.secs[0].state, 2 * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
-    for (size_t i = 0; i < active.size(); ++i) active[i]->last_active = st[2 * i + 1];
+    for (size_t i = 0; i < active.size(); ++i) active[i]->last_active = state_host[2 * i + 1];
     rounds.fetch_add(1);
     peak.store(heap.peak);
     return FTLM_OK;
@@ -363,6 +381,8 @@ int ftlm_server_create(void* arena_dev, size_t arena_bytes, const ftlm_server_op
     if (int rc = check_dtype(opts->dtype)) return rc;
     if (opts->max_active < 0 || opts->max_active > kServerMaxActive)
         return fail(FTLM_E_RANGE, "max_active %d not in [0, %d]", opts->max_active, kServerMaxActive);
+    if (opts->steps_per_round < 0 || opts->steps_per_round > kServerMaxSteps)
+        return fail(FTLM_E_RANGE, "steps_per_round %d not in [0, %d]", opts->steps_per_round, kServerMaxSteps);
     if (reinterpret_cast<uintptr_t>(arena_dev) % 256 != 0) return fail(FTLM_E_INVALID, "arena not 256-byte aligned");
     const size_t desc = align256(size_t(kServerMaxActive) * sizeof(SecWork));
     if (arena_bytes <= desc) return fail(FTLM_E_NOSPACE, "arena smaller than its descriptor area (%zu bytes)", desc);
@@ -372,9 +392,15 @@ int ftlm_server_create(void* arena_dev, size_t arena_bytes, const ftlm_server_op
     s->opts = *opts;
     s->t0 = std::chrono::steady_clock::now();
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->desc_host), size_t(kServerMaxActive) * sizeof(SecWork));
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->state_host), size_t(kServerMaxActive) * 2 * sizeof(int32_t));
     if (e != hipSuccess) {
+        if (s->desc_host) (void)hipHostFree(s->desc_host);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
         delete s;
-        return fail(FTLM_E_DEVICE, "stream: %s", hipGetErrorString(e));
+        return fail(FTLM_E_DEVICE, "server setup: %s", hipGetErrorString(e));
     }
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -475,6 +501,8 @@ void ftlm_server_destroy(ftlm_server* s) {
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->desc_host) (void)hipHostFree(s->desc_host);
+    if (s->state_host) (void)hipHostFree(s->state_host);
     delete s;
 }
 

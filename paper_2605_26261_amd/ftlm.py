@@ -98,7 +98,7 @@ class PlanTuning(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     """ftlm_server_opts."""
     _fields_ = [("mode", ctypes.c_int32), ("dtype", ctypes.c_int32), ("max_active", ctypes.c_int32),
-                ("batch_same_n", ctypes.c_int32)]
+                ("batch_same_n", ctypes.c_int32), ("steps_per_round", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -374,9 +374,10 @@ def server_request_bytes(n_sites, bonds, n_up, R, M, mode, dtype, temps=(1.0,)):
 class Server:
     """ftlm_server: continuous-batching FTLM request server over a device arena."""
 
-    def __init__(self, arena_bytes, mode=CR, dtype=F32, max_active=0, batch_same_n=True, device="cuda"):
+    def __init__(self, arena_bytes, mode=CR, dtype=F32, max_active=0, batch_same_n=True, device="cuda",
+                 steps_per_round=0):
         self.arena = _empty_device(arena_bytes, device)
-        opts = ServerOpts(mode, dtype, max_active, 1 if batch_same_n else 0)
+        opts = ServerOpts(mode, dtype, max_active, 1 if batch_same_n else 0, steps_per_round)
         h = _vp()
         _check(_lib.ftlm_server_create(_dptr(self.arena), self.arena.numel(), ctypes.byref(opts), ctypes.byref(h)))
         self.handle = h
