@@ -179,3 +179,19 @@ def test_thermo_rejects_bad_input(ftlm):
     rec["steps"] = np.array([2], dtype=np.int32)
     with pytest.raises(ftlm.FtlmError):
         ftlm.thermo(2, [rec], [0.0])
+
+
+def test_server_options_validated_before_any_device_work(ftlm):
+    # options are checked before the arena is touched or a stream is made, so
+    # a placeholder (256-byte aligned, never dereferenced) arena address will do
+    h = ctypes.c_void_p()
+    fake_arena = ctypes.c_void_p(1 << 20)
+    for kw, code in (({"steps_per_round": 65}, ftlm.E_RANGE), ({"steps_per_round": -1}, ftlm.E_RANGE),
+                     ({"max_active": 257}, ftlm.E_RANGE), ({"mode": 5}, ftlm.E_INVALID),
+                     ({"dtype": 9}, ftlm.E_INVALID)):
+        args = {"mode": ftlm.CR, "dtype": ftlm.F32, "max_active": 0, "batch_same_n": 1, "steps_per_round": 0}
+        args.update(kw)
+        opts = ftlm.ServerOpts(**args)
+        rc = ftlm._lib.ftlm_server_create(fake_arena, 1 << 30, ctypes.byref(opts), ctypes.byref(h))
+        assert rc == code, (kw, rc)
+        assert not h.value

@@ -57,11 +57,13 @@ def _direct(ftlm, driver, req, mode, dtype):
     return ftlm.thermo(req["n_sites"], [rec], TEMPS, 1.0)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_served_equals_direct(env, mode):
+@pytest.mark.parametrize("mode,steps_per_round", [(0, 0), (1, 0), (1, 1), (1, 7)])
+def test_served_equals_direct(env, mode, steps_per_round):
+    # several Lanczos steps per round: requests finish inside a round and
+    # their remaining launches must leave them untouched
     torch, ftlm, driver = env
     reqs = _small_stream(8, seed=11)
-    srv = ftlm.Server(1 << 30, mode=mode, dtype=ftlm.F32)
+    srv = ftlm.Server(1 << 30, mode=mode, dtype=ftlm.F32, steps_per_round=steps_per_round)
     ids = [srv.submit(q["n_sites"], q["bonds"], q["n_up"], q["R"], q["M"], q["seed"], ftlm.PM1, TEMPS) for q in reqs]
     res = _wait_all(srv, ids)
     for q, rid in zip(reqs, ids):
