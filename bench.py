@@ -31,11 +31,12 @@ N_SITES, N_UP, R, M, SEED = 30, 15, 20, 100, 2
 
 
 # HBM bytes per steady-state launch of the dominant kernel (Lanczos-epilogue
-# H.x over 20 FP32 columns), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
-# scaled by the counts of a 2 GiB copy (profiles/hv_lanczos_n30_r20_counters.md).
-# They describe the kernel sources with this hash and are dropped otherwise.
+# H.x over the autotuned block of FP32 columns, `batch`), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs scaled by the counts of a 2 GiB copy
+# (profiles/hv_lanczos_n30_r20_counters.md). They describe the kernel sources
+# with this hash at that block width and are dropped otherwise.
 KERNEL_SOURCES = ["layout.hpp", "device.hpp", "kernels.hpp", "rowloop.hpp", "hv_impl.hpp", "hv_f32.hip"]
-MEASURED_TRAFFIC = {"sources": "c9ceace97e309305", "batch": 20, "bytes": {"clt": 406.49e9, "cr": 347.37e9}}
+MEASURED_TRAFFIC = {"sources": "6773e7db8061166d", "batch": 10, "bytes": {"clt": 176.20e9, "cr": 157.16e9}}
 
 
 def kernel_source_hash():
@@ -169,7 +170,7 @@ def run_gpu(args):
         del work
         torch.cuda.empty_cache()
         sweep = {}
-        for nv in (1, 4, 8, 16, 20, 32):
+        for nv in (1, 4, 8, 10, 16, 20, 32):
             x = torch.randn((dim, nv) if nv > 1 else (dim,), dtype=torch.float32, device=dev)
             y = torch.empty_like(x)
             ms = timed_hv(ftlm, torch, sec, g, x, y, 20)
@@ -356,11 +357,13 @@ def cpu_baseline(target_s=15.0):
                       f"(count-based ranks, no stored basis), {dt:.1f} s"}
 
 
-def profile_kernels(batch):
+def profile_kernels(batch=None):
     """Short run for hardware-counter passes: per index map, a 3-step Lanczos
-    run over `batch` chains (3 Lanczos-epilogue H.x launches and 3 updates)
-    and 3 single-vector H.x launches; then an elementwise kernel that reads
-    2 GiB and writes 2 GiB, to calibrate the byte counters."""
+    run over `batch` chains (the autotuner's choice for R chains when None,
+    picked first, so the run's last two Lanczos-epilogue H.x launches are the
+    steady-state launches of the FTLM pass) and 3 single-vector H.x launches;
+    then an elementwise kernel that reads 2 GiB and writes 2 GiB, to
+    calibrate the byte counters."""
     import torch
 
     from ftlm_inputs import graphs
@@ -370,7 +373,13 @@ def profile_kernels(batch):
     g = ftlm.Graph(N_SITES, graphs.icosidodecahedron())
     for mode in (ftlm.CLT, ftlm.CR):
         sec = ftlm.Sector(N_SITES, N_UP, mode, device=dev)
-        ftlm.lanczos(sec, g, SEED, 0, batch, 3, ftlm.GAUSS, ftlm.F32)
+        B = batch
+        if B is None:
+            work = torch.empty(ftlm.lanczos_workspace_bytes(sec, R, ftlm.F32), dtype=torch.uint8, device=dev)
+            B = int(ftlm.autotune(sec, g, R, ftlm.F32, work=work)["batch"])
+            del work
+        log("profile: batch", B)
+        ftlm.lanczos(sec, g, SEED, 0, B, 3, ftlm.GAUSS, ftlm.F32)
         x = torch.randn(sec.dim, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
         for _ in range(3):
@@ -403,7 +412,7 @@ def main():
                     help="run one secondary measurement alone and print its JSON (for kernel traces)")
     args = ap.parse_args()
     if args.profile_kernels:
-        profile_kernels(R if args.batch == "auto" else int(args.batch))
+        profile_kernels(None if args.batch == "auto" else int(args.batch))
         return
     if args.only:
         run = {"plan": plan_vs_plain, "largest": largest_sector,

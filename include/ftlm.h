@@ -235,7 +235,7 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
  * batched Lanczos; the paper picks B adaptively, Sec. 3.4). ftlm_autotune
  * times one Lanczos step of B chains of the sector (the multi-vector H.x in
  * the form ftlm_lanczos would run it, and the vector update) at candidate
- * batch widths B in {1, 2, 4, 8, 16, 20, 32} (B <= R) with HIP events on
+ * batch widths B in {1, 2, 4, 8, 10, 16, 20, 32} (B <= R; FP64 up to 16) with HIP events on
  * `stream`, using
  * work_dev (at least ftlm_lanczos_workspace_bytes(s, R, dtype) bytes) as
  * scratch, and returns the B that minimizes the time of one Lanczos step of
@@ -292,7 +292,7 @@ int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_gr
 /* ftlm_plan_tune: chooses how the plan's R columns are split into kernel
  * launches (the vector-block widths of the batched Lanczos step, Sec. 3.4).
  * Candidates are the widest-first splits into launches of at most 32, 20,
- * 16, 8 and 4 columns (FP64: 16, 8, 4), distinct ones only; each is timed
+ * 16, 10, 8 and 4 columns (FP64: 16, 8, 4), distinct ones only; each is timed
  * over one Lanczos step of the whole plan, after a warm-up step, with HIP
  * events on the plan's stream (ordered after the work on `stream`), twice,
  * keeping the faster time. The fastest candidate is kept for later

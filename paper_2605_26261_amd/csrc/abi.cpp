@@ -393,7 +393,7 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
         }
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int widths[] = {1, 2, 4, 8, 16, 20, 32};
+    const int widths[] = {1, 2, 4, 8, 10, 16, 20, 32};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -614,9 +614,9 @@ int ftlm_plan_tune(ftlm_plan* p, void* stream, ftlm_plan_tuning* out) {
     HIP_CHECK(hipEventCreate(&ev.e1));
     HIP_CHECK(hipEventRecord(p->ready, static_cast<hipStream_t>(stream)));
     HIP_CHECK(hipStreamWaitEvent(p->stream, p->ready, 0));
-    static const int caps32[] = {32, 20, 16, 8, 4}, caps64[] = {16, 8, 4};
+    static const int caps32[] = {32, 20, 16, 10, 8, 4}, caps64[] = {16, 8, 4};
     const int* caps = p->dtype == FTLM_F32 ? caps32 : caps64;
-    const int ncap = p->dtype == FTLM_F32 ? 5 : 3;
+    const int ncap = p->dtype == FTLM_F32 ? 6 : 3;
     const auto previous = p->job.chunks;
     std::vector<std::vector<std::pair<int, int>>> seen;
     ftlm_plan_tuning t{};

@@ -527,6 +527,9 @@ hipError_t with_vb(int vb, F&& f) {
         case 4: return f(std::integral_constant<int, 4>{});
         case 8: return f(std::integral_constant<int, 8>{});
         case 16: return f(std::integral_constant<int, 16>{});
+        case 10:
+            if constexpr (sizeof(T) == 4) return f(std::integral_constant<int, 10>{});
+            else return hipErrorInvalidValue;
         case 20:
             if constexpr (sizeof(T) == 4) return f(std::integral_constant<int, 20>{});
             else return hipErrorInvalidValue;

@@ -158,7 +158,7 @@ def _rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("nvec", [1, 2, 3, 4, 6, 8, 16, 20, 32])
+@pytest.mark.parametrize("nvec", [1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 32])
 @pytest.mark.parametrize("n,bonds", [(12, graphs.icosahedron()), (16, graphs.random_cluster(16, np.random.default_rng(2))),
                                      (20, graphs.dodecahedron())])
 def test_hv_parity_multivector(env, nvec, n, bonds):
