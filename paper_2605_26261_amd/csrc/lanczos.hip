@@ -122,18 +122,19 @@ __global__ __launch_bounds__(kBlock) void start_kernel(LanczosLaunch a) {
 // stopping rule: a chain stops after step k when k reaches min(M, D) or
 // beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}). A stopped chain gets
 // zero scales, so its columns stay zero in every later step.
-// Blocks whose rows are 48 to 128 bytes (a multiple of 16) go through LDS:
-// the rows of u and w staged together are contiguous, so they move with fully
-// coalesced 16-byte accesses, while each thread still updates its own row (the
-// same arithmetic and summation order as without the staging). With one
-// thread per row, a 16-byte access of rows that wide spans several cache lines
-// per wave; narrower rows are already well coalesced. Rows of up to 96 bytes
-// are staged a whole tile at a time, 128-byte rows half a tile at a time (two
-// 256-row tiles would not fit the static LDS); without the staging, 128-byte
-// rows ran at under 1 TB/s.
+// Blocks whose rows are 40 to 128 bytes (a multiple of 8) go through LDS: the
+// rows of u and w staged together are contiguous, so they move with fully
+// coalesced 16-byte accesses (8-byte ones for rows that are not a multiple of
+// 16 bytes), while each thread still updates its own row (the same arithmetic
+// and summation order as without the staging). With one thread per row, a
+// vector access of rows that wide spans several cache lines per wave; narrower
+// rows are already well coalesced. Rows of up to 96 bytes are staged a whole
+// tile at a time, 128-byte rows half a tile at a time (two 256-row tiles
+// would not fit the static LDS); without the staging, 128-byte rows ran at
+// under 1 TB/s and 40-byte rows at 4.0 TB/s.
 template <typename T, int VB>
 __host__ __device__ constexpr bool update_staged() {
-    return (VB * sizeof(T)) % 16 == 0 && VB * sizeof(T) >= 48 && VB * sizeof(T) <= 128;
+    return (VB * sizeof(T)) % 8 == 0 && VB * sizeof(T) >= 40 && VB * sizeof(T) <= 128;
 }
 
 template <typename T, int VB>
@@ -178,15 +179,17 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
             if (staged) {
                 const uint32_t t0 = tile * kBlock;
                 const uint32_t rows = dim - t0 < uint32_t(kBlock) ? dim - t0 : uint32_t(kBlock);
-                using V16 = uint32_t __attribute__((ext_vector_type(4)));  // 16 bytes
-                V16* lu = reinterpret_cast<V16*>(stage_u);
-                V16* lw = reinterpret_cast<V16*>(stage_w);
+                // copy unit: 16 bytes, or 8 for rows of an odd number of 8-byte words
+                constexpr int kUnit = (VB * sizeof(T)) % 16 == 0 ? 4 : 2;
+                using VU = uint32_t __attribute__((ext_vector_type(kUnit)));
+                VU* lu = reinterpret_cast<VU*>(stage_u);
+                VU* lw = reinterpret_cast<VU*>(stage_w);
                 // rows [h0, h0 + hr) of the tile at a time (block-uniform bounds)
                 for (uint32_t h0 = 0; h0 < rows; h0 += uint32_t(kStageRows)) {
                     const uint32_t hr = rows - h0 < uint32_t(kStageRows) ? rows - h0 : uint32_t(kStageRows);
-                    const uint32_t n16 = hr * uint32_t(VB * sizeof(T)) / 16u;
-                    const V16 FTLM_GLOBAL* gu = gptr(reinterpret_cast<const V16*>(u + uint64_t(t0 + h0) * VB));
-                    V16 FTLM_GLOBAL* gw = gptr(reinterpret_cast<V16*>(w + uint64_t(t0 + h0) * VB));
+                    const uint32_t n16 = hr * uint32_t(VB * sizeof(T)) / uint32_t(4 * kUnit);
+                    const VU FTLM_GLOBAL* gu = gptr(reinterpret_cast<const VU*>(u + uint64_t(t0 + h0) * VB));
+                    VU FTLM_GLOBAL* gw = gptr(reinterpret_cast<VU*>(w + uint64_t(t0 + h0) * VB));
                     for (uint32_t i = threadIdx.x; i < n16; i += kBlock) {
                         lu[i] = gu[i];
                         lw[i] = gw[i];
