@@ -394,9 +394,8 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int widths[] = {1, 2, 4, 8, 10, 16, 20, 32};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_CHECK(hipEventCreate(&e0));
-    HIP_CHECK(hipEventCreate(&e1));
+    EventPair ev;
+    HIP_CHECK(ev.create());
     double best = 1e300;
     int best_b = 1;
     int n = 0;
@@ -410,17 +409,13 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
         for (int rep = 0; rep < 3; ++rep) {
             int rc = job_start(job, 0, 0, FTLM_PM1, st);
             if (rc == FTLM_OK) rc = job_steps(job, st, false, 1);
-            if (rc == FTLM_OK && hipEventRecord(e0, st) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc == FTLM_OK && hipEventRecord(ev.e0, st) != hipSuccess) rc = FTLM_E_DEVICE;
             if (rc == FTLM_OK) rc = job_steps(job, st, false, 1);
-            if (rc == FTLM_OK && hipEventRecord(e1, st) != hipSuccess) rc = FTLM_E_DEVICE;
-            if (rc == FTLM_OK && hipEventSynchronize(e1) != hipSuccess) rc = FTLM_E_DEVICE;
-            if (rc != FTLM_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return rc == FTLM_E_DEVICE ? fail(rc, "autotune: HIP error") : rc;
-            }
+            if (rc == FTLM_OK && hipEventRecord(ev.e1, st) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc == FTLM_OK && hipEventSynchronize(ev.e1) != hipSuccess) rc = FTLM_E_DEVICE;
+            if (rc != FTLM_OK) return rc == FTLM_E_DEVICE ? fail(rc, "autotune: HIP error") : rc;
             float ms = 0.f;
-            HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            HIP_CHECK(hipEventElapsedTime(&ms, ev.e0, ev.e1));
             if (rep > 0) best_ms = std::min(best_ms, ms);  // the first rep warms up
         }
         const double step = double((R + B - 1) / B) * double(best_ms);
@@ -432,8 +427,6 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
             best_b = B;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     out->n_candidates = n;
     out->batch = best_b;
     out->ms_per_step = best;
@@ -603,15 +596,8 @@ int ftlm_plan_run(ftlm_plan* p, uint64_t seed, uint64_t r0, int dist, int use_gr
 
 int ftlm_plan_tune(ftlm_plan* p, void* stream, ftlm_plan_tuning* out) {
     if (!p) return fail(FTLM_E_INVALID, "null argument");
-    struct Events {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        ~Events() {
-            if (e0) (void)hipEventDestroy(e0);
-            if (e1) (void)hipEventDestroy(e1);
-        }
-    } ev;
-    HIP_CHECK(hipEventCreate(&ev.e0));
-    HIP_CHECK(hipEventCreate(&ev.e1));
+    EventPair ev;
+    HIP_CHECK(ev.create());
     HIP_CHECK(hipEventRecord(p->ready, static_cast<hipStream_t>(stream)));
     HIP_CHECK(hipStreamWaitEvent(p->stream, p->ready, 0));
     static const int caps32[] = {32, 20, 16, 10, 8, 4}, caps64[] = {16, 8, 4};

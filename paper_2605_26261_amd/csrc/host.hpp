@@ -57,6 +57,22 @@ int ok();
 
 uint64_t binom_u64(int n, int k);
 
+// Two timing events destroyed on every exit path.
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t create() {
+        hipError_t e = hipEventCreate(&e0);
+        return e == hipSuccess ? hipEventCreate(&e1) : e;
+    }
+    EventPair() = default;
+    EventPair(const EventPair&) = delete;
+    EventPair& operator=(const EventPair&) = delete;
+    ~EventPair() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 // Bond tables and the two-pass split (split.cpp).
 BondTable make_bond_table(int n_sites, const std::vector<int>& lo, const std::vector<int>& hi,
                           const std::vector<double>& J, const std::vector<int>& orig, double jsum_all);
@@ -82,7 +98,15 @@ struct HvTimer {
     explicit HvTimer(hipStream_t s) : st(s) {
         std::lock_guard<std::mutex> lk(g_stats.mu);
         if (!g_stats.on) return;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        if (hipEventCreate(&a) != hipSuccess) {
+            a = nullptr;
+            return;
+        }
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = b = nullptr;
+            return;
+        }
         (void)hipEventRecord(a, st);
     }
     ~HvTimer() {
