@@ -196,9 +196,9 @@ class Graph:
         _check(_lib.ftlm_graph_split(self.handle, _hptr(order), ctypes.byref(c), ctypes.byref(s)))
         return order, c.value, s.value
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ftlm_graph_destroy):
         if getattr(self, "handle", None):
-            _lib.ftlm_graph_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 
@@ -224,9 +224,9 @@ class Sector:
     def dim(self):
         return int(_lib.ftlm_sector_dim(self.handle))
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ftlm_sector_destroy):
         if getattr(self, "handle", None):
-            _lib.ftlm_sector_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 
@@ -347,9 +347,9 @@ class Plan:
         cands = {int(t.max_width[i]): (int(t.n_launches[i]), float(t.ms[i])) for i in range(t.n_candidates)}
         return {"candidates": cands, "max_width": int(t.max_width[t.chosen])}
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ftlm_plan_destroy):
         if getattr(self, "handle", None):
-            _lib.ftlm_plan_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
 
@@ -413,9 +413,9 @@ class Server:
         _check(_lib.ftlm_server_stats(self.handle, ctypes.byref(peak), ctypes.byref(rounds), ctypes.byref(active)))
         return {"peak_bytes": peak.value, "rounds": rounds.value, "active": active.value}
 
-    def close(self):
+    def close(self, _destroy=_lib.ftlm_server_destroy):
         if getattr(self, "handle", None):
-            _lib.ftlm_server_destroy(self.handle)
+            _destroy(self.handle)
             self.handle = None
 
     def __del__(self):
