@@ -436,6 +436,10 @@ def main():
             "kernel": f"hv_lanczos_kernel<uint32, {best.upper()}, float, {dom['batch']}> (Lanczos-epilogue H.x "
                       f"over {dom['batch']} FP32 columns)",
             "alg_bytes_per_launch": dom["hv_alg_bytes"], "avg_launch_ms": dom["hv_avg_ms"]}
+    # counted HBM traffic of the same launch over its measured duration
+    counted_gbs = traffic / (dom["hv_avg_ms"] * 1e-3) / 1e9 if traffic else None
+    roof["counted_gbs"] = counted_gbs
+    roof["counted_frac"] = counted_gbs / HBM_PEAK_GBS if counted_gbs else None
     out = {
         "metric": METRIC,
         "value": r["states_bonds_per_s"],
@@ -454,6 +458,7 @@ def main():
                    "index_mode": best},
         "samples_per_s": r["samples_per_s"],
         "hbm_gbs_alg": dom["hv_alg_gbs"],
+        "hbm_gbs_counted": counted_gbs,
         "modes": results,
         "roofline": roof,
     }
