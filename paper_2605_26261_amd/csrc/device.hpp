@@ -149,8 +149,9 @@ __device__ __forceinline__ void clt_bonds(uint32_t n, const BondTable& B, const 
             for (int g = 0; g < G; ++g) {
                 const uint32_t lo = B.lo(b + g), hi = B.hi(b + g);
                 anti[g] = ((n >> lo) & 1u) != ((n >> hi) & 1u);
-                m[g] = anti[g] ? n ^ ((1u << lo) | (1u << hi)) : n;
-                e[g] = clt_entry(clt, m[g] >> 5);
+                m[g] = n ^ ((1u << lo) | (1u << hi));
+                e[g] = CltEntry{0u, 0u};
+                if (anti[g]) e[g] = clt_entry(clt, m[g] >> 5);
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) idx[g] = e[g].prefix + __popc(e[g].mask & ((1u << (m[g] & 31u)) - 1u));

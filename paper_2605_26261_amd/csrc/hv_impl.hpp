@@ -122,8 +122,12 @@ struct GatherVisitor {
         T v[kGroup][VB];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-            const uint32_t i = idx[g] < last ? idx[g] : last;
-            load_row<T, VB>(x + uint64_t(i) * ld + col0, v[g]);
+#pragma unroll
+            for (int i = 0; i < VB; ++i) v[g][i] = T(0);
+            if (flips[g]) {
+                const uint32_t i = idx[g] < last ? idx[g] : last;
+                load_row<T, VB>(x + uint64_t(i) * ld + col0, v[g]);
+            }
         }
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
