@@ -25,6 +25,12 @@ NONE = (1 << 64) - 1
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libftlm.so not found at {LIB_PATH}: build it with paper_2605_26261_amd/build.py")
 
+# torch ships its own HIP runtime. It has to be the one in the process before
+# libftlm.so is loaded, so that the library binds to it: a system HIP runtime
+# loaded first leaves one of the two without the device ("no ROCm-capable
+# device") once torch starts its own.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 _vp, _u64, _i32, _i64, _sz, _dbl = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64,

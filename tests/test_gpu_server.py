@@ -133,3 +133,27 @@ def test_served_against_oracle(env):
             scale = np.max(np.abs(want[key]))
             assert np.all(np.abs(res[rid][key] - want[key]) <= 1e-4 * scale + 1e-12)
     srv.close()
+
+
+def test_binding_imported_before_torch(env):
+    # a fresh process that loads the binding before anything imports torch:
+    # the library must still share torch's HIP runtime (a server is the
+    # first object whose setup calls HIP directly)
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2605_26261_amd import ftlm\n"
+            "from ftlm_inputs import graphs\n"
+            "s = ftlm.Server(1 << 28, mode=ftlm.CR, dtype=ftlm.F32)\n"
+            "rid = s.submit(10, graphs.ring(10), 5, 4, 20, 1, ftlm.PM1, [1.0])\n"
+            "import time\n"
+            "t0 = time.time()\n"
+            "while s.poll(rid) is None:\n"
+            "    assert time.time() - t0 < 60\n"
+            "    time.sleep(0.001)\n"
+            "s.close()\n"
+            "print('served')\n") % root
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=110)
+    assert r.returncode == 0 and "served" in r.stdout, r.stderr[-2000:]
