@@ -131,11 +131,12 @@ struct BondTable {
 //   v.flip(b, idx)  for an antiparallel bond b (b in the sorted order), and
 //   v.par(b)        for a parallel one;
 // or, when the visitor takes groups (V::kGroup > 1), v.group(b0, idx, flips)
-// for kGroup consecutive bonds at a time (CLT), and v.site_group(b0, idx,
-// flips, count) for up to V::kSiteGroup bonds of one lower site (CR). A group has no branch on the spins:
-// every lane looks up a label (its own for a parallel bond, giving its own
-// index), so the group's table loads and then its row gathers are all in
-// flight together; the visitor weighs parallel bonds by zero.
+// for kGroup consecutive bonds at a time (CLT). In CR (cr_bonds below) a
+// visitor takes up to V::kSiteGroup bonds of one lower site at a time, as
+// v.issue(b0, idx, flips, count) (two groups in flight, V::kPipe) or
+// v.site_group(b0, idx, flips, count). A group's table loads and then its row
+// gathers are in flight together; lanes whose bond is parallel issue neither,
+// and the visitor weighs them by zero.
 template <typename V>
 __device__ __forceinline__ void clt_bonds(uint32_t n, const BondTable& B, const CltEntry* __restrict__ clt, V& v) {
     int b = 0;
@@ -211,7 +212,28 @@ __device__ __forceinline__ L cr_bonds(uint32_t t, L n_in, int n_up, const BondTa
         }
         ylds[p * 64] = Y;
         const int end = int(B.ends[p]);
-        if constexpr (V::kSiteGroup > 1) {
+        if constexpr (V::kPipe) {
+            // the bonds whose lower site is p, V::kSiteGroup at a time, issued
+            // before the previous group is accumulated
+            constexpr int G = V::kSiteGroup;
+            for (; b < end; b += G) {
+                const int cnt = end - b < G ? end - b : G;
+                uint32_t idx[G];
+                bool anti[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    anti[g] = false;
+                    idx[g] = t;
+                    if (g < cnt) {
+                        const uint32_t hb = B.hi(b + g);
+                        anti[g] = uint32_t((n >> hb) & 1) != uint32_t(one);
+                        if (anti[g]) idx[g] = t + X + ylds[hb * 64];
+                    }
+                }
+                v.issue(b, idx, anti, cnt);
+            }
+            b = end;
+        } else if constexpr (V::kSiteGroup > 1) {
             // the bonds whose lower site is p, V::kSiteGroup at a time: their
             // gathers go out together before any of them is consumed
             constexpr int G = V::kSiteGroup;
@@ -241,6 +263,7 @@ __device__ __forceinline__ L cr_bonds(uint32_t t, L n_in, int n_up, const BondTa
             }
         }
     }
+    if constexpr (V::kPipe) v.finish();
     return n;
 }
 

@@ -87,36 +87,74 @@ struct GatherVisitor {
         anti += c;
     }
     __device__ __forceinline__ void par(int) {}
-    // A group of kGroup consecutive bonds: all rows are loaded (a parallel
-    // bond's index is the row itself), then accumulated with weight J_b / 2
-    // or zero.
+    // CLT: a group of kGroup consecutive bonds: the rows of the antiparallel
+    // ones are loaded together (lanes whose bond is parallel load nothing),
+    // then accumulated with weight J_b / 2 or zero.
     static constexpr int kGroup = VB >= 16 ? 2 : 4;
-    static constexpr int kSiteGroup = VB > 20 ? 1 : (VB >= 16 ? 2 : 4);
-    // Up to kSiteGroup bonds of one lower site (count is wave-uniform): the
-    // rows of the antiparallel ones are loaded together (lanes whose bond is
-    // parallel load nothing), then accumulated in bond order.
-    __device__ __forceinline__ void site_group(int b0, const uint32_t (&idx)[kSiteGroup],
-                                               const bool (&flips)[kSiteGroup], int count) {
-        T v[kSiteGroup][VB];
+    // CR: bonds of one lower site in groups of kSiteGroup, two groups deep
+    // (issue / finish below) for blocks of up to 20 columns; wider blocks take
+    // one bond at a time (flip / par).
+    static constexpr bool kPipe = VB <= 20;
+    static constexpr int kSiteGroup = VB >= 10 ? 1 : 2;
+    // Two group buffers that take turns: one is loading while the other, issued
+    // before it, is accumulated. Rows are zero in lanes whose bond is parallel
+    // (those lanes load nothing); `phase` (wave-uniform) names the buffer the
+    // next group loads into. The turns are separate code paths, so a buffer's
+    // registers are never read before they are accumulated.
+    T bufa[kSiteGroup][VB], bufb[kSiteGroup][VB];
+    T coefa[kSiteGroup], coefb[kSiteGroup];
+    int cnta = 0, cntb = 0;
+    bool phase = false;
+    __device__ __forceinline__ void load_group(T (&buf)[kSiteGroup][VB], T (&coef)[kSiteGroup], int b0,
+                                               const uint32_t (&idx)[kSiteGroup], const bool (&flips)[kSiteGroup],
+                                               int count) {
 #pragma unroll
         for (int g = 0; g < kSiteGroup; ++g) {
 #pragma unroll
-            for (int i = 0; i < VB; ++i) v[g][i] = T(0);
-            if (g < count && flips[g]) {
-                const uint32_t i = idx[g] < last ? idx[g] : last;
-                load_row<T, VB>(x + uint64_t(i) * ld + col0, v[g]);
+            for (int i = 0; i < VB; ++i) buf[g][i] = T(0);
+            coef[g] = T(0);
+            if (g < count) {
+                if (flips[g]) {
+                    const uint32_t i = idx[g] < last ? idx[g] : last;
+                    load_row<T, VB>(x + uint64_t(i) * ld + col0, buf[g]);
+                }
+                const T cb = bond_coef<T>(B, b0 + g);
+                coef[g] = flips[g] ? cb : T(0);
             }
         }
+    }
+    __device__ __forceinline__ void add_group(const T (&buf)[kSiteGroup][VB], const T (&coef)[kSiteGroup],
+                                              int count) {
 #pragma unroll
         for (int g = 0; g < kSiteGroup; ++g) {
             if (g < count) {
-                const T cb = bond_coef<T>(B, b0 + g);
-            const T c = flips[g] ? cb : T(0);
 #pragma unroll
-                for (int i = 0; i < VB; ++i) acc[i] += c * v[g][i];
-                anti += c;
+                for (int i = 0; i < VB; ++i) acc[i] += coef[g] * buf[g][i];
+                anti += coef[g];
             }
         }
+    }
+    // Loads a group, then accumulates the group issued before it (bond order).
+    __device__ __forceinline__ void issue(int b0, const uint32_t (&idx)[kSiteGroup],
+                                          const bool (&flips)[kSiteGroup], int count) {
+        if (!phase) {
+            load_group(bufa, coefa, b0, idx, flips, count);
+            add_group(bufb, coefb, cntb);
+            cnta = count;
+            cntb = 0;
+        } else {
+            load_group(bufb, coefb, b0, idx, flips, count);
+            add_group(bufa, coefa, cnta);
+            cntb = count;
+            cnta = 0;
+        }
+        phase = !phase;
+    }
+    // Accumulates the last group issued.
+    __device__ __forceinline__ void finish() {
+        if (phase) add_group(bufa, coefa, cnta);
+        else add_group(bufb, coefb, cntb);
+        cnta = cntb = 0;
     }
     __device__ __forceinline__ void group(int b0, const uint32_t (&idx)[kGroup], const bool (&flips)[kGroup]) {
         T v[kGroup][VB];
