@@ -30,13 +30,18 @@ HBM_PEAK_GBS = 8000.0
 N_SITES, N_UP, R, M, SEED = 30, 15, 20, 100, 2
 
 
+# block widths of one FP32 Lanczos-epilogue H.x launch
+LAUNCH_WIDTHS_F32 = (1, 2, 4, 8, 10, 12, 16, 20, 32)
+
 # HBM bytes per steady-state launch of the dominant kernel (Lanczos-epilogue
-# H.x over the autotuned block of FP32 columns, `batch`), from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs scaled by the counts of a 2 GiB copy
-# (profiles/hv_lanczos_n30_r20_counters.md). They describe the kernel sources
-# with this hash at that block width and are dropped otherwise.
+# H.x over a block of FP32 columns, per index map and block width), from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by the counts of a 2 GiB
+# copy (profiles/hv_lanczos_n30_r20_counters.md). They describe the kernel
+# sources with this hash and are dropped otherwise.
 KERNEL_SOURCES = ["layout.hpp", "device.hpp", "kernels.hpp", "rowloop.hpp", "hv_impl.hpp", "hv_f32.hip"]
-MEASURED_TRAFFIC = {"sources": "ca93157b511750fa", "batch": 10, "bytes": {"clt": 166.35e9, "cr": 154.06e9}}
+MEASURED_TRAFFIC = {"sources": "35355df27d5e1c37", "bytes": {
+    "clt": {1: 19.14e9, 2: 34.92e9, 4: 67.68e9, 8: 126.16e9, 10: 166.34e9, 12: 206.28e9, 16: 279.85e9, 20: 378.79e9},
+    "cr": {1: 12.83e9, 2: 26.92e9, 4: 55.23e9, 8: 117.12e9, 10: 154.54e9, 12: 192.72e9, 16: 250.3e9, 20: 317.4e9}}}
 
 
 def kernel_source_hash():
@@ -170,7 +175,7 @@ def run_gpu(args):
         del work
         torch.cuda.empty_cache()
         sweep = {}
-        for nv in (1, 4, 8, 10, 16, 20, 32):
+        for nv in (1, 4, 8, 10, 12, 16, 20, 32):
             x = torch.randn((dim, nv) if nv > 1 else (dim,), dtype=torch.float32, device=dev)
             y = torch.empty_like(x)
             ms = timed_hv(ftlm, torch, sec, g, x, y, 20)
@@ -359,11 +364,11 @@ def cpu_baseline(target_s=15.0):
 
 def profile_kernels(batch=None):
     """Short run for hardware-counter passes: per index map, a 3-step Lanczos
-    run over `batch` chains (the autotuner's choice for R chains when None,
-    picked first, so the run's last two Lanczos-epilogue H.x launches are the
-    steady-state launches of the FTLM pass) and 3 single-vector H.x launches;
-    then an elementwise kernel that reads 2 GiB and writes 2 GiB, to
-    calibrate the byte counters."""
+    run over `batch` chains (when None, one at every FP32 launch width up to
+    R, so that whichever width the autotuner picks, the last two
+    Lanczos-epilogue H.x launches of its run are steady-state launches of the
+    FTLM pass) and 3 single-vector H.x launches; then an elementwise kernel
+    that reads 2 GiB and writes 2 GiB, to calibrate the byte counters."""
     import torch
 
     from ftlm_inputs import graphs
@@ -373,13 +378,9 @@ def profile_kernels(batch=None):
     g = ftlm.Graph(N_SITES, graphs.icosidodecahedron())
     for mode in (ftlm.CLT, ftlm.CR):
         sec = ftlm.Sector(N_SITES, N_UP, mode, device=dev)
-        B = batch
-        if B is None:
-            work = torch.empty(ftlm.lanczos_workspace_bytes(sec, R, ftlm.F32), dtype=torch.uint8, device=dev)
-            B = int(ftlm.autotune(sec, g, R, ftlm.F32, work=work)["batch"])
-            del work
-        log("profile: batch", B)
-        ftlm.lanczos(sec, g, SEED, 0, B, 3, ftlm.GAUSS, ftlm.F32)
+        for B in ([batch] if batch else [w for w in LAUNCH_WIDTHS_F32 if w <= R]):
+            log("profile: batch", B)
+            ftlm.lanczos(sec, g, SEED, 0, B, 3, ftlm.GAUSS, ftlm.F32)
         x = torch.randn(sec.dim, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
         for _ in range(3):
@@ -428,8 +429,8 @@ def main():
     r = results[best]
     dom = results[best]
     traffic = None
-    if kernel_source_hash() == MEASURED_TRAFFIC["sources"] and dom["batch"] == MEASURED_TRAFFIC["batch"]:
-        traffic = MEASURED_TRAFFIC["bytes"][best]
+    if kernel_source_hash() == MEASURED_TRAFFIC["sources"]:
+        traffic = MEASURED_TRAFFIC["bytes"].get(best, {}).get(dom["batch"])
     roof = {"bound": "hbm", "achieved": dom["hv_alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom["hv_alg_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "bytes per launch (HBM fetch + write, counter-calibrated)",

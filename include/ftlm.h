@@ -234,12 +234,14 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
  * The B chains of a Lanczos batch share each row's index work (Sec. 2,
  * batched Lanczos; the paper picks B adaptively, Sec. 3.4). ftlm_autotune
  * times one Lanczos step of B chains of the sector (the multi-vector H.x in
- * the form ftlm_lanczos would run it, and the vector update) at candidate
- * batch widths B in {1, 2, 4, 8, 10, 16, 20, 32} (B <= R; FP64 up to 16) with HIP events on
- * `stream`, using
+ * the form ftlm_lanczos would run it, and the vector update) at every launch
+ * width B <= R: {1, 2, 4, 8, 10, 12, 16, 20, 32} for FP32, {1, 2, 4, 8, 16}
+ * for FP64, with HIP events on `stream`, using
  * work_dev (at least ftlm_lanczos_workspace_bytes(s, R, dtype) bytes) as
- * scratch, and returns the B that minimizes the time of one Lanczos step of
- * all R chains run in ceil(R / B) batches. Results are cached per (N, n_up,
+ * scratch. It returns the B that minimizes the time of one Lanczos step of
+ * all R chains run as floor(R / B) batches of B and one of R mod B, each
+ * batch priced as the sum of its column chunks (the launch widths
+ * ftlm_lanczos cuts it into). Results are cached per (N, n_up,
  * bonds, mode, dtype, R, split policy) for the life of the process; the file named by the
  * environment variable FTLM_AUTOTUNE_CACHE, when set, is read and appended
  * (one "key batch ms" line per entry). The workgroup grid is not tuned: it
@@ -247,8 +249,8 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
 typedef struct ftlm_tuning {
     int32_t batch;          /* chains per ftlm_lanczos call */
     int32_t n_candidates;
-    int32_t widths[8];      /* candidate B */
-    double ms[8];           /* measured step milliseconds at each B */
+    int32_t widths[12];     /* candidate B (n_candidates of them) */
+    double ms[12];          /* measured step milliseconds at each B */
     double ms_per_step;     /* predicted step time of all R chains at `batch` */
     int32_t cached;         /* 1 when served from the cache */
 } ftlm_tuning;

@@ -335,10 +335,12 @@ struct TuneCache {
     std::map<std::string, std::pair<int, double>> entries;
 } g_tune;
 
+// "_c2": the candidate set and cost model; a cache file written under an
+// older one is not reused.
 std::string tune_key(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype) {
     std::string k = "N" + std::to_string(s->n_sites) + "_u" + std::to_string(s->n_up) + "_m" +
                     std::to_string(s->mode) + "_t" + std::to_string(dtype) + "_R" + std::to_string(R) + "_p" +
-                    std::to_string(g_split_policy) + "_b";
+                    std::to_string(g_split_policy) + "_c2_b";
     // the bond structure, so that two graphs with the same size do not share entries
     uint64_t h = 1469598103934665603ull;
     for (size_t b = 0; b < g->bi.size(); ++b) {
@@ -393,14 +395,14 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
         }
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int widths[] = {1, 2, 4, 8, 10, 16, 20, 32};
+    // every width a Lanczos launch can take (FP32 only: 10, 12, 20, 32), so
+    // that a batch of any size is priced from launches that were measured
+    const int widths[] = {1, 2, 4, 8, 10, 12, 16, 20, 32};
     EventPair ev;
     HIP_CHECK(ev.create());
-    double best = 1e300;
-    int best_b = 1;
     int n = 0;
     for (int B : widths) {
-        if (B > R || (dtype == FTLM_F64 && B > 16)) continue;
+        if (B > R || (dtype == FTLM_F64 && (B > 16 || B == 10 || B == 12))) continue;
         // B chains of the sector (their state fits the workspace sized for
         // R >= B); two Lanczos steps per repetition, the first one a warm-up
         LanczosJob job;
@@ -418,13 +420,31 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
             HIP_CHECK(hipEventElapsedTime(&ms, ev.e0, ev.e1));
             if (rep > 0) best_ms = std::min(best_ms, ms);  // the first rep warms up
         }
-        const double step = double((R + B - 1) / B) * double(best_ms);
         out->widths[n] = B;
         out->ms[n] = best_ms;
         ++n;
+    }
+    // A batch of x chains runs as the column chunks ftlm_lanczos cuts for it;
+    // its step costs the measured steps of those widths.
+    auto measured = [&](int w) {
+        for (int i = 0; i < n; ++i)
+            if (out->widths[i] == w) return out->ms[i];
+        return 1e300;  // not reached: every chunk width is a candidate <= R
+    };
+    auto batch_ms = [&](int x) {
+        double t = 0.0;
+        for (auto [col, w] : column_chunks_v(x, uint64_t(x), dtype, {})) t += measured(w);
+        return t;
+    };
+    // R chains in batches of b: R / b full batches and one of R mod b
+    double best = 1e300;
+    int best_b = 1;
+    for (int i = 0; i < n; ++i) {
+        const int b = out->widths[i];
+        const double step = double(R / b) * batch_ms(b) + (R % b ? batch_ms(R % b) : 0.0);
         if (step < best) {
             best = step;
-            best_b = B;
+            best_b = b;
         }
     }
     out->n_candidates = n;

@@ -62,10 +62,10 @@ Stats g_stats;
 std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtype, const std::vector<const void*>& ptrs,
                                                  int max_width) {
     const size_t es = dtype == FTLM_F32 ? 4 : 8;
-    static const int w32[] = {32, 20, 16, 10, 8, 4, 2, 1};
+    static const int w32[] = {32, 20, 16, 12, 10, 8, 4, 2, 1};
     static const int w64[] = {16, 8, 4, 2, 1};
     const int* widths = dtype == FTLM_F32 ? w32 : w64;
-    const int nw = dtype == FTLM_F32 ? 8 : 5;
+    const int nw = dtype == FTLM_F32 ? 9 : 5;
     std::vector<std::pair<int, int>> out;
     int col = 0;
     while (col < nvec) {

@@ -572,6 +572,9 @@ hipError_t with_vb(int vb, F&& f) {
         case 10:
             if constexpr (sizeof(T) == 4) return f(std::integral_constant<int, 10>{});
             else return hipErrorInvalidValue;
+        case 12:
+            if constexpr (sizeof(T) == 4) return f(std::integral_constant<int, 12>{});
+            else return hipErrorInvalidValue;
         case 20:
             if constexpr (sizeof(T) == 4) return f(std::integral_constant<int, 20>{});
             else return hipErrorInvalidValue;

@@ -87,8 +87,8 @@ _sig("ftlm_stats_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_dou
 
 class Tuning(ctypes.Structure):
     """ftlm_tuning."""
-    _fields_ = [("batch", ctypes.c_int32), ("n_candidates", ctypes.c_int32), ("widths", ctypes.c_int32 * 8),
-                ("ms", ctypes.c_double * 8), ("ms_per_step", ctypes.c_double), ("cached", ctypes.c_int32)]
+    _fields_ = [("batch", ctypes.c_int32), ("n_candidates", ctypes.c_int32), ("widths", ctypes.c_int32 * 12),
+                ("ms", ctypes.c_double * 12), ("ms_per_step", ctypes.c_double), ("cached", ctypes.c_int32)]
 
 
 _sig("ftlm_autotune", _i32, [_vp, _vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(Tuning)])

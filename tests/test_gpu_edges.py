@@ -126,7 +126,7 @@ def test_sectors_smaller_than_a_tile(env, n, n_up, mode):
     d = sec.dim
     assert d < 256
     b = oracle.basis(n, n_up)
-    for nvec in (1, 2, 4, 8, 10, 16, 20, 32):
+    for nvec in (1, 2, 4, 8, 10, 12, 16, 20, 32):
         dtypes = ((torch.float32, 1e-5), (torch.float64, 1e-13)) if nvec <= 16 else ((torch.float32, 1e-5),)
         x64 = rng.standard_normal((d, nvec))
         for dtype, tol in dtypes:

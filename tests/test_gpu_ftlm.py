@@ -203,7 +203,13 @@ def test_autotune_choice_does_not_change_results(env):
     g = ftlm.Graph(n, bonds)
     sec = ftlm.Sector(n, n_up, ftlm.CR)
     t = ftlm.autotune(sec, g, R, ftlm.F32)
-    assert t["batch"] in t["candidates"] and set(t["candidates"]) == {1, 2, 4, 8, 10}
+    assert t["batch"] in t["candidates"] and set(t["candidates"]) == {1, 2, 4, 8, 10, 12}
+    # the choice minimizes R // b full batches plus one of R % b (each a
+    # single launch here: every remainder of 12 is a candidate width)
+    ms = t["candidates"]
+    cost = {b: (R // b) * ms[b] + (ms[R % b] if R % b else 0.0) for b in ms}
+    assert t["ms_per_step"] == pytest.approx(cost[t["batch"]], rel=1e-12)
+    assert cost[t["batch"]] == min(cost.values())
     assert not t["cached"]
     t2 = ftlm.autotune(sec, g, R, ftlm.F32)
     assert t2["cached"] and t2["batch"] == t["batch"]
@@ -214,11 +220,11 @@ def test_autotune_choice_does_not_change_results(env):
         np.testing.assert_array_equal(auto[0]["beta"], fixed[0]["beta"])
 
 
-@pytest.mark.parametrize("block", [20, 10])
+@pytest.mark.parametrize("block", [20, 12, 10, 8])
 def test_icosidodecahedron_twenty_column_block(env, block):
     # The launch configurations the benchmark times: the 20 chains of the
-    # N = 30 workload in one block, or in two blocks of 10 (the autotuner's
-    # choice on MI355X). The first two chains equal the 2-chain run bit for
+    # N = 30 workload in one block, in blocks of 12 and 8, or in two blocks
+    # of 10 (the autotuner picks among these). The first two chains equal the 2-chain run bit for
     # bit (a chain does not depend on its batch) and agree with the stored
     # FP64 oracle reference at FP32 roundoff, in both index maps.
     path = os.path.join(GOLDEN, "icosidodecahedron_r2.json")
