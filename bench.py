@@ -39,9 +39,9 @@ LAUNCH_WIDTHS_F32 = (1, 2, 4, 8, 10, 12, 16, 20, 32)
 # copy (profiles/hv_lanczos_n30_r20_counters.md). They describe the kernel
 # sources with this hash and are dropped otherwise.
 KERNEL_SOURCES = ["layout.hpp", "device.hpp", "kernels.hpp", "rowloop.hpp", "hv_impl.hpp", "hv_f32.hip"]
-MEASURED_TRAFFIC = {"sources": "35355df27d5e1c37", "bytes": {
-    "clt": {1: 19.14e9, 2: 34.92e9, 4: 67.68e9, 8: 126.16e9, 10: 166.34e9, 12: 206.28e9, 16: 279.85e9, 20: 378.79e9},
-    "cr": {1: 12.83e9, 2: 26.92e9, 4: 55.23e9, 8: 117.12e9, 10: 154.54e9, 12: 192.72e9, 16: 250.3e9, 20: 317.4e9}}}
+MEASURED_TRAFFIC = {"sources": "7318781b68d46eea", "bytes": {
+    "clt": {1: 19.11e9, 2: 34.76e9, 4: 67.57e9, 8: 126.29e9, 10: 166.25e9, 12: 206.54e9, 16: 280.07e9, 20: 378.51e9},
+    "cr": {1: 12.81e9, 2: 26.94e9, 4: 55.15e9, 8: 117.11e9, 10: 154.75e9, 12: 192.33e9, 16: 250.61e9, 20: 317.46e9}}}
 
 
 def kernel_source_hash():

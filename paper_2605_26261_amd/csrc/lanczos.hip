@@ -122,19 +122,23 @@ __global__ __launch_bounds__(kBlock) void start_kernel(LanczosLaunch a) {
 // stopping rule: a chain stops after step k when k reaches min(M, D) or
 // beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}). A stopped chain gets
 // zero scales, so its columns stay zero in every later step.
-// Blocks whose rows are 40 to 128 bytes (a multiple of 8) go through LDS: the
+// Blocks whose rows are 32 to 128 bytes (a multiple of 8) go through LDS: the
 // rows of u and w staged together are contiguous, so they move with fully
 // coalesced 16-byte accesses (8-byte ones for rows that are not a multiple of
 // 16 bytes), while each thread still updates its own row (the same arithmetic
 // and summation order as without the staging). With one thread per row, a
-// vector access of rows that wide spans several cache lines per wave; narrower
-// rows are already well coalesced. Rows of up to 96 bytes are staged a whole
-// tile at a time, 128-byte rows half a tile at a time (two 256-row tiles
-// would not fit the static LDS); without the staging, 128-byte rows ran at
-// under 1 TB/s and 40-byte rows at 4.0 TB/s.
+// vector access of rows that wide spans several cache lines per wave;
+// narrower rows are already well coalesced. Rows of up to 96 bytes are staged
+// a whole tile at a time, 128-byte rows half a tile at a time (two 256-row
+// tiles would not fit the static LDS). A block loads its next chunk into
+// registers before it stores the current one, so its reads stay in flight
+// while it writes; every byte is touched once per step, so the accesses are
+// non-temporal. Without the staging, 128-byte rows ran at under 1 TB/s and
+// 40-byte rows at 4.0 TB/s; staged without the prefetch, 48-byte rows ran at
+// 4.7 TB/s, and with it at 5.1 TB/s.
 template <typename T, int VB>
 __host__ __device__ constexpr bool update_staged() {
-    return (VB * sizeof(T)) % 8 == 0 && VB * sizeof(T) >= 40 && VB * sizeof(T) <= 128;
+    return (VB * sizeof(T)) % 8 == 0 && VB * sizeof(T) >= 32 && VB * sizeof(T) <= 128;
 }
 
 template <typename T, int VB>
@@ -173,45 +177,83 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
     const uint32_t ntiles = (dim + kBlock - 1) / kBlock;
     // whole rows of [D][ld] blocks: a tile is one contiguous range
     const bool staged = kStage && a.col0 == 0 && a.ld == uint64_t(VB);
+    if constexpr (kStage) {
+        if (staged) {
+            // copy unit: 16 bytes, or 8 for rows of an odd number of 8-byte words
+            constexpr int kUnit = (VB * sizeof(T)) % 16 == 0 ? 4 : 2;
+            using VU = uint32_t __attribute__((ext_vector_type(kUnit)));
+            constexpr uint32_t kRowUnits = uint32_t(VB * sizeof(T)) / uint32_t(4 * kUnit);
+            constexpr int kPer = int((uint32_t(kStageRows) * kRowUnits + kBlock - 1) / kBlock);
+            VU* lu = reinterpret_cast<VU*>(stage_u);
+            VU* lw = reinterpret_cast<VU*>(stage_w);
+            // A chunk is rows [h0, h0 + hr) of one tile; the block walks its
+            // tiles in for_each_tile's order. The next chunk's rows are loaded
+            // into registers while the current chunk is stored.
+            VU pu[kPer], pw[kPer];
+            auto tile_rows = [&](uint32_t tile) {
+                return dim - tile * kBlock < uint32_t(kBlock) ? dim - tile * kBlock : uint32_t(kBlock);
+            };
+            auto chunk_units = [&](uint32_t tile, uint32_t h0) {
+                const uint32_t left = tile_rows(tile) - h0;
+                return (left < uint32_t(kStageRows) ? left : uint32_t(kStageRows)) * kRowUnits;
+            };
+            auto fetch = [&](uint32_t tile, uint32_t h0) {
+                const uint32_t n = chunk_units(tile, h0);
+                const uint64_t r0 = uint64_t(tile) * kBlock + h0;
+                const VU FTLM_GLOBAL* gu = gptr(reinterpret_cast<const VU*>(u + r0 * VB));
+                const VU FTLM_GLOBAL* gw = gptr(reinterpret_cast<const VU*>(w + r0 * VB));
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t i = threadIdx.x + uint32_t(k) * kBlock;
+                    if (i < n) {
+                        pu[k] = __builtin_nontemporal_load(gu + i);
+                        pw[k] = __builtin_nontemporal_load(gw + i);
+                    }
+                }
+            };
+            const TileSpan sp = tile_span(ntiles, local, sw.G);
+            uint32_t tile = sp.first, h0 = 0;
+            if (tile < sp.end) fetch(tile, h0);
+            while (tile < sp.end) {
+                const uint32_t n = chunk_units(tile, h0);
+                const uint32_t hr = n / kRowUnits;
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t i = threadIdx.x + uint32_t(k) * kBlock;
+                    if (i < n) {
+                        lu[i] = pu[k];
+                        lw[i] = pw[k];
+                    }
+                }
+                __syncthreads();
+                // each thread updates the row it owns (row threadIdx.x of the tile)
+                if (threadIdx.x >= h0 && threadIdx.x < h0 + hr) {
+                    T* wr = stage_w + (threadIdx.x - h0) * VB;
+                    const T* ur = stage_u + (threadIdx.x - h0) * VB;
+#pragma unroll
+                    for (int c = 0; c < VB; ++c) {
+                        const T v = wr[c] - coef[c] * ur[c];
+                        part[c] += double(v) * double(v);
+                        wr[c] = v;
+                    }
+                }
+                __syncthreads();
+                VU FTLM_GLOBAL* gw = gptr(reinterpret_cast<VU*>(w + (uint64_t(tile) * kBlock + h0) * VB));
+                h0 += uint32_t(kStageRows);
+                if (h0 >= tile_rows(tile)) {
+                    h0 = 0;
+                    tile += sp.step;
+                }
+                if (tile < sp.end) fetch(tile, h0);
+                for (uint32_t i = threadIdx.x; i < n; i += kBlock) __builtin_nontemporal_store(lw[i], gw + i);
+                __syncthreads();
+            }
+        }
+    }
     for_each_tile(ntiles, local, sw.G, [&](uint32_t tile) {
         const uint32_t t = tile * kBlock + threadIdx.x;
         if constexpr (kStage) {
-            if (staged) {
-                const uint32_t t0 = tile * kBlock;
-                const uint32_t rows = dim - t0 < uint32_t(kBlock) ? dim - t0 : uint32_t(kBlock);
-                // copy unit: 16 bytes, or 8 for rows of an odd number of 8-byte words
-                constexpr int kUnit = (VB * sizeof(T)) % 16 == 0 ? 4 : 2;
-                using VU = uint32_t __attribute__((ext_vector_type(kUnit)));
-                VU* lu = reinterpret_cast<VU*>(stage_u);
-                VU* lw = reinterpret_cast<VU*>(stage_w);
-                // rows [h0, h0 + hr) of the tile at a time (block-uniform bounds)
-                for (uint32_t h0 = 0; h0 < rows; h0 += uint32_t(kStageRows)) {
-                    const uint32_t hr = rows - h0 < uint32_t(kStageRows) ? rows - h0 : uint32_t(kStageRows);
-                    const uint32_t n16 = hr * uint32_t(VB * sizeof(T)) / uint32_t(4 * kUnit);
-                    const VU FTLM_GLOBAL* gu = gptr(reinterpret_cast<const VU*>(u + uint64_t(t0 + h0) * VB));
-                    VU FTLM_GLOBAL* gw = gptr(reinterpret_cast<VU*>(w + uint64_t(t0 + h0) * VB));
-                    for (uint32_t i = threadIdx.x; i < n16; i += kBlock) {
-                        lu[i] = gu[i];
-                        lw[i] = gw[i];
-                    }
-                    __syncthreads();
-                    // each thread updates the row it owns (row threadIdx.x of the tile)
-                    if (threadIdx.x >= h0 && threadIdx.x < h0 + hr) {
-                        T* wr = stage_w + (threadIdx.x - h0) * VB;
-                        const T* ur = stage_u + (threadIdx.x - h0) * VB;
-#pragma unroll
-                        for (int c = 0; c < VB; ++c) {
-                            const T v = wr[c] - coef[c] * ur[c];
-                            part[c] += double(v) * double(v);
-                            wr[c] = v;
-                        }
-                    }
-                    __syncthreads();
-                    for (uint32_t i = threadIdx.x; i < n16; i += kBlock) gw[i] = lw[i];
-                    __syncthreads();
-                }
-                return;
-            }
+            if (staged) return;  // done above
         }
         if (t >= dim) return;
         T uu[VB], ww[VB];

@@ -6,11 +6,30 @@
 
 namespace ftlm {
 
-// Calls f(tile) for the tiles of kBlock rows owned by block `bid` of a
-// (sub-)grid of G blocks. With G a multiple of 8 and the sub-grid starting
-// at a multiple of 8, block i runs on XCD i mod 8 (round-robin dispatch), so
-// XCD x gets the x-th contiguous eighth of the tiles and its L2 sees
-// neighbouring rows; inside a share the XCD's blocks stride.
+// The tiles of kBlock rows owned by block `bid` of a (sub-)grid of G blocks:
+// first, first + step, ... below end. With G a multiple of 8 and the
+// sub-grid starting at a multiple of 8, block i runs on XCD i mod 8
+// (round-robin dispatch), so XCD x gets the x-th contiguous eighth of the
+// tiles and its L2 sees neighbouring rows; inside a share the XCD's blocks
+// stride.
+struct TileSpan {
+    uint32_t first, end, step;
+};
+
+__device__ __forceinline__ TileSpan tile_span(uint32_t ntiles, uint32_t bid, uint32_t G) {
+    if (G >= 8 && (G & 7u) == 0) {
+        const uint32_t chunk = (ntiles + 7u) >> 3;
+        const uint32_t begin = (bid & 7u) * chunk;
+        return {begin + (bid >> 3), begin + chunk < ntiles ? begin + chunk : ntiles, G >> 3};
+    }
+    return {bid, ntiles, G};
+}
+
+// Calls f(tile) for the tiles of block `bid`, in tile_span's order. The loop
+// is written out rather than built on tile_span: that form lowers the
+// register count of several H.x kernels by 4-6 VGPRs, enough to lift some to
+// one more wave per SIMD, where their gathers thrash the caches (the plain
+// 32-column CR H.x ran 28 % slower).
 template <typename F>
 __device__ __forceinline__ void for_each_tile(uint32_t ntiles, uint32_t bid, uint32_t G, F&& f) {
     if (G >= 8 && (G & 7u) == 0) {
