@@ -10,6 +10,9 @@
   at every kernel width, against the FP64 oracle.
 * Vector blocks whose base pointer or row stride is not 16-byte aligned run
   on the narrower kernel widths and give the same product.
+* The Lanczos update's two paths (rows staged through LDS when a launch
+  covers whole rows, per-thread strided rows when it covers part of a wider
+  block) give bitwise the same chains, at every staged row size.
 """
 
 import numpy as np
@@ -213,3 +216,38 @@ def test_rank_outside_sector_is_the_sentinel(env, mode):
     ftlm.rank(sec, lt, idx)
     got = idx.cpu().numpy().view(np.uint64)
     assert [int(v) for v in got] == [int(v) for v in want]
+
+
+# (dtype, R of the wide block, [(r0, width) of each of its column chunks]):
+# inside the wide block every chunk runs the strided update; alone, as a
+# block of its own width, it runs the staged one (32- to 128-byte rows:
+# 8 FP32 columns 32 B, 10 40 B, 12 48 B, 20 80 B, 32 128 B (half tiles);
+# FP64 4 columns 32 B, 16 128 B).
+UPDATE_SPLITS = [
+    ("f32", 28, [(0, 20), (20, 8)]),
+    ("f32", 44, [(0, 32), (32, 12)]),
+    ("f32", 30, [(0, 10), (10, 10), (20, 10)]),
+    ("f64", 20, [(0, 16), (16, 4)]),
+]
+
+
+@pytest.mark.parametrize("dt,R,chunks", UPDATE_SPLITS)
+def test_staged_and_strided_updates_agree(env, dt, R, chunks):
+    # N = 24, S^z = 0: D = 2,704,156 rows, several 256-row tiles per
+    # workgroup and a ragged last tile of 28 rows. A chain depends on its
+    # sample index r0 + r only, so columns [r0, r0 + w) of the wide run equal
+    # a w-chain run started at r0, bit for bit.
+    torch, ftlm = env
+    dtype = ftlm.F32 if dt == "f32" else ftlm.F64
+    n, n_up, M, seed = 24, 12, 8, 41
+    g = ftlm.Graph(n, graphs.square_j1j2(6, 4, 1.0, 0.5))
+    sec = ftlm.Sector(n, n_up, ftlm.CR)
+    assert sec.dim % 256 == 28
+    a, b, s = ftlm.lanczos(sec, g, seed, 0, R, M, ftlm.GAUSS, dtype)
+    assert sum(w for _, w in chunks) == R
+    for r0, w in chunks:
+        a1, b1, s1 = ftlm.lanczos(sec, g, seed, r0, w, M, ftlm.GAUSS, dtype)
+        np.testing.assert_array_equal(a[r0:r0 + w], a1)
+        np.testing.assert_array_equal(b[r0:r0 + w], b1)
+        np.testing.assert_array_equal(s[r0:r0 + w], s1)
+    assert np.all(s == M) and np.all(b[:, : M - 1] > 0)
