@@ -396,6 +396,17 @@ void ftlm_server_destroy(ftlm_server* s);
  * Wilkinson shifts, FP64, on the host (Sec. 2: the tridiagonal problem is
  * solved on the host in FP64). */
 int ftlm_ritz(int m, const double* alpha, const double* beta, double* theta, double* weight);
+/* ftlm_ritz_batch: ftlm_ritz for the n chains of one FTLM run at once, on
+ * host threads (the R samples of Sec. 2 are independent). alpha, beta, theta
+ * and weight are [n][stride] host arrays; chain r uses the first m[r]
+ * entries of its alpha row and m[r] - 1 of its beta row (1 <= m[r] <=
+ * stride) and gets theta and weight in its first m[r] entries, zeros in the
+ * rest. Each chain is solved exactly as ftlm_ritz solves it, so the results
+ * do not depend on the thread count. FTLM_E_INVALID for a bad argument or a
+ * chain whose QL iteration does not converge (the other rows are still
+ * written). */
+int ftlm_ritz_batch(int n, int stride, const int32_t* m, const double* alpha, const double* beta, double* theta,
+                    double* weight);
 
 /* One sector's Lanczos samples for ftlm_thermo. theta and weight are
  * [R][stride] host arrays; sample r uses its first steps[r] entries. */

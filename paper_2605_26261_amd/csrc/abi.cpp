@@ -682,6 +682,18 @@ int ftlm_ritz(int m, const double* alpha, const double* beta, double* theta, dou
     return ok();
 }
 
+int ftlm_ritz_batch(int n, int stride, const int32_t* m, const double* alpha, const double* beta, double* theta,
+                    double* weight) {
+    if (n < 0 || stride < 1) return fail(FTLM_E_INVALID, "n = %d, stride = %d", n, stride);
+    if (n == 0) return ok();
+    if (!m || !alpha || !beta || !theta || !weight) return fail(FTLM_E_INVALID, "null argument");
+    for (int r = 0; r < n; ++r)
+        if (m[r] < 1 || m[r] > stride) return fail(FTLM_E_INVALID, "chain %d: m = %d outside [1, %d]", r, m[r], stride);
+    if (ritz_batch(n, stride, m, alpha, beta, theta, weight) != 0)
+        return fail(FTLM_E_INVALID, "QL iteration did not converge");
+    return ok();
+}
+
 int ftlm_thermo(int n_sites, int n_sectors, const ftlm_sector_result* sectors, int nT, const double* T, double g,
                 double* E, double* C, double* chi, double* lnZ) {
     if (n_sectors < 1 || !sectors || nT < 0 || (nT && !T)) return fail(FTLM_E_INVALID, "bad argument");

@@ -2,13 +2,64 @@
 // tridiagonal matrix and the thermal reduction (paper Sec. 2: the small
 // tridiagonal problem is solved on the host in FP64; Eqs. 4-9).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <numeric>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "host_math.hpp"
 
 namespace ftlm {
+
+namespace {
+
+// sqrt(a^2 + b^2): the plain formula where it can neither overflow nor lose
+// precision to underflow, std::hypot (several times slower) elsewhere.
+inline double givens_norm(double a, double b) {
+    const double x = std::fabs(a), y = std::fabs(b);
+    const double big = x > y ? x : y;
+    if (big > 1e-150 && big < 1e150) return std::sqrt(a * a + b * b);
+    return std::hypot(a, b);
+}
+
+// Calls f(i) for i in [0, n), split into contiguous ranges over up to
+// `threads` host threads (the calling one included). Every index is handled
+// by one thread alone, so results do not depend on the split; a thread that
+// cannot be started leaves its range to the caller.
+template <typename F>
+void parallel_for(int n, int threads, F&& f) {
+    threads = std::max(1, std::min(threads, n));
+    const int per = threads > 1 ? (n + threads - 1) / threads : n;
+    std::vector<std::thread> pool;
+    std::vector<std::pair<int, int>> left;
+    for (int t = 1; t < threads; ++t) {
+        const int b = t * per, e = std::min(n, b + per);
+        if (b >= e) break;
+        try {
+            pool.emplace_back([&f, b, e] {
+                for (int i = b; i < e; ++i) f(i);
+            });
+        } catch (const std::system_error&) {
+            left.emplace_back(b, e);
+        }
+    }
+    for (int i = 0; i < std::min(n, per); ++i) f(i);
+    for (auto [b, e] : left)
+        for (int i = b; i < e; ++i) f(i);
+    for (auto& th : pool) th.join();
+}
+
+// Host threads for `work` elementary steps: one below about a millisecond of
+// work (thread start-up would dominate), else up to 16.
+int host_threads(double work) {
+    if (work < 2e5) return 1;
+    const unsigned hw = std::thread::hardware_concurrency();
+    return int(std::min(16u, hw ? hw : 1u));
+}
+
+}  // namespace
 
 // Implicit-shift QL iteration on the symmetric tridiagonal matrix with
 // diagonal d[0..m-1] and off-diagonal e[i] coupling rows i and i+1. Each
@@ -32,13 +83,13 @@ int ritz_ql(int m, const double* alpha, const double* beta, double* theta, doubl
             if (iter >= 200) return -1;
             // shift toward d[l] from the leading 2x2 block
             double g = (d[size_t(l + 1)] - d[size_t(l)]) / (2.0 * e[size_t(l)]);
-            double r = std::hypot(g, 1.0);
+            double r = givens_norm(g, 1.0);
             g = d[size_t(k)] - d[size_t(l)] + e[size_t(l)] / (g + std::copysign(r, g));
             double s = 1.0, c = 1.0, p = 0.0;
             bool deflated = false;
             for (int i = k - 1; i >= l; --i) {
                 const double f = s * e[size_t(i)], b = c * e[size_t(i)];
-                r = std::hypot(f, g);
+                r = givens_norm(f, g);
                 e[size_t(i + 1)] = r;
                 if (r == 0.0) {  // the block split: finish this sweep early
                     d[size_t(i + 1)] -= p;
@@ -74,6 +125,20 @@ int ritz_ql(int m, const double* alpha, const double* beta, double* theta, doubl
     return 0;
 }
 
+int ritz_batch(int n, int stride, const int32_t* m, const double* alpha, const double* beta, double* theta,
+               double* weight) {
+    std::atomic<int> failed{0};
+    double work = 0.0;
+    for (int r = 0; r < n; ++r) work += double(m[r]) * double(m[r]);
+    parallel_for(n, host_threads(4.0 * work), [&](int r) {
+        const size_t o = size_t(r) * size_t(stride);
+        const int k = m[r];
+        if (ritz_ql(k, alpha + o, beta + o, theta + o, weight + o) != 0) failed.store(1);
+        for (int j = k; j < stride; ++j) theta[o + size_t(j)] = weight[o + size_t(j)] = 0.0;
+    });
+    return failed.load() ? -1 : 0;
+}
+
 // FTLM thermal reduction (Eqs. 6-9). Per sector the estimator weighs each
 // sample's Gauss-quadrature sum by mult * D / R; Boltzmann factors use
 // theta - E0 with E0 the smallest Ritz value of all samples, which cancels in
@@ -86,7 +151,12 @@ int thermo(int n_sites, int n_sectors, const SectorSamples* sec, int nT, const d
             for (int k = 0; k < sec[s].steps[r]; ++k)
                 e0 = std::min(e0, sec[s].theta[size_t(r) * size_t(sec[s].stride) + size_t(k)]);
     if (!std::isfinite(e0)) return -1;
-    for (int it = 0; it < nT; ++it) {
+    double work = 0.0;
+    for (int s = 0; s < n_sectors; ++s)
+        for (int r = 0; r < sec[s].R; ++r) work += double(sec[s].steps[r]);
+    // temperatures are independent: each is summed by one thread, in the
+    // same order whatever the split
+    parallel_for(nT, host_threads(work * double(nT)), [&](int it) {
         const double beta = 1.0 / T[it];
         double z = 0.0, h1 = 0.0, h2 = 0.0, zm2 = 0.0;
         for (int s = 0; s < n_sectors; ++s) {
@@ -115,7 +185,7 @@ int thermo(int n_sites, int n_sectors, const SectorSamples* sec, int nT, const d
         if (C) C[it] = beta * beta * (h2 / z - mean * mean);
         if (chi) chi[it] = g * g * beta * zm2 / z;
         if (lnZ) lnZ[it] = std::log(z) - beta * e0;
-    }
+    });
     return 0;
 }
 

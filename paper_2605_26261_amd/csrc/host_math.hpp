@@ -18,6 +18,12 @@ struct SectorSamples {
 
 int ritz_ql(int m, const double* alpha, const double* beta, double* theta, double* weight);
 
+// ritz_ql for chains r = 0 .. n-1 of [n][stride] arrays (chain r: its first
+// m[r] entries; theta and weight from m[r] on are zeroed), on host threads.
+// Returns -1 if any chain fails to converge.
+int ritz_batch(int n, int stride, const int32_t* m, const double* alpha, const double* beta, double* theta,
+               double* weight);
+
 int thermo(int n_sites, int n_sectors, const SectorSamples* sec, int nT, const double* T,
            double g, double* E, double* C, double* chi, double* lnZ);
 

@@ -20,14 +20,7 @@ def log_temperatures(n=200, t_min=0.05, t_max=10.0):
 
 def records_from_coefficients(n_sites, n_up, dim, alpha, beta, steps):
     """Host Ritz solves of R chains -> a thermo record of the sector."""
-    R, M = alpha.shape
-    theta = np.zeros((R, M))
-    weight = np.zeros((R, M))
-    for r in range(R):
-        k = int(steps[r])
-        th, w = ftlm.ritz(alpha[r, :k], beta[r, :max(k - 1, 1)], k)
-        theta[r, :k] = th
-        weight[r, :k] = w
+    theta, weight = ftlm.ritz_batch(alpha, beta, steps)
     return {"n_up": n_up, "dim": dim, "mult": multiplicity(n_sites, n_up), "theta": theta, "weight": weight,
             "steps": np.asarray(steps), "alpha": alpha, "beta": beta}
 

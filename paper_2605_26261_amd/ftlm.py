@@ -79,6 +79,7 @@ _sig("ftlm_plan_run", _i32, [_vp, _u64, _u64, _i32, _i32, _vp, _vp, _vp, _vp])
 _sig("ftlm_plan_tune", _i32, [_vp, _vp, _vp])
 _sig("ftlm_plan_destroy", None, [_vp])
 _sig("ftlm_ritz", _i32, [_i32, _vp, _vp, _vp, _vp])
+_sig("ftlm_ritz_batch", _i32, [_i32, _i32, _vp, _vp, _vp, _vp, _vp])
 _sig("ftlm_thermo", _i32, [_i32, _i32, ctypes.POINTER(SectorResult), _i32, _vp, _dbl, _vp, _vp, _vp, _vp])
 _sig("ftlm_stats_enable", _i32, [_i32])
 _sig("ftlm_stats_reset", _i32, [])
@@ -436,6 +437,22 @@ def ritz(alpha, beta, m=None):
     theta = np.empty(m, dtype=np.float64)
     weight = np.empty(m, dtype=np.float64)
     _check(_lib.ftlm_ritz(m, _hptr(alpha), _hptr(beta), _hptr(theta), _hptr(weight)))
+    return theta, weight
+
+
+def ritz_batch(alpha, beta, steps):
+    """ftlm_ritz_batch: Ritz values and weights of every chain of [R][M]
+    alpha/beta rows, chain r over its first steps[r] entries; returns [R][M]
+    theta and weight (zeros past steps[r])."""
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    R, M = alpha.shape
+    if beta.shape != (R, M) or steps.shape != (R,):
+        raise ValueError("alpha and beta must be [R][M] and steps [R]")
+    theta = np.empty((R, M), dtype=np.float64)
+    weight = np.empty((R, M), dtype=np.float64)
+    _check(_lib.ftlm_ritz_batch(R, M, _hptr(steps), _hptr(alpha), _hptr(beta), _hptr(theta), _hptr(weight)))
     return theta, weight
 
 

@@ -146,6 +146,57 @@ def test_ritz_on_a_lanczos_matrix_with_ghosts(ftlm):
         assert abs((w * th ** p).sum() - (w_o * th_o ** p).sum()) < 1e-9 * max(1, abs((w_o * th_o ** p).sum()))
 
 
+def test_ritz_batch_equals_single_chain_solves(ftlm):
+    # enough chains to run on several host threads; ragged step counts (1 to
+    # M), one chain with a split block; every chain bit for bit as ftlm_ritz
+    # gives it, zeros past its steps
+    rng = np.random.default_rng(21)
+    R, M = 40, 60
+    a = rng.standard_normal((R, M)) * 2
+    b = np.abs(rng.standard_normal((R, M))) + 0.05
+    b[7, 20] = 1e-300
+    steps = rng.integers(1, M + 1, R).astype(np.int32)
+    steps[:3] = (1, M, 2)
+    steps[7] = M
+    th, w = ftlm.ritz_batch(a, b, steps)
+    for r in range(R):
+        k = int(steps[r])
+        t1, w1 = ftlm.ritz(a[r, :k], b[r, :max(k - 1, 1)], k)
+        np.testing.assert_array_equal(th[r, :k], t1)
+        np.testing.assert_array_equal(w[r, :k], w1)
+        assert not th[r, k:].any() and not w[r, k:].any()
+        assert abs(w[r, :k].sum() - 1.0) < 1e-13
+
+
+def test_ritz_batch_rejects_bad_input(ftlm):
+    a = np.ones((2, 5))
+    for bad in ((0, 5), (5, 6), (-1, 3)):
+        with pytest.raises(ftlm.FtlmError) as e:
+            ftlm.ritz_batch(a, a, np.array(bad, dtype=np.int32))
+        assert e.value.code == ftlm.E_INVALID
+    th, w = ftlm.ritz_batch(np.ones((0, 5)), np.ones((0, 5)), np.zeros(0, dtype=np.int32))
+    assert th.shape == (0, 5)
+
+
+def test_thermo_does_not_depend_on_the_thread_split(ftlm):
+    # a grid large enough to be split over host threads gives, at every
+    # temperature, bit for bit what a one-temperature call gives
+    rng = np.random.default_rng(22)
+    recs = []
+    for n_up in range(8, 12):
+        th = np.sort(rng.standard_normal((32, 60)) * 4, axis=1)
+        w = rng.random((32, 60))
+        w /= w.sum(axis=1, keepdims=True)
+        recs.append({"n_up": n_up, "dim": math.comb(16, n_up), "mult": 1.0 if n_up == 8 else 2.0, "theta": th,
+                     "weight": w, "steps": np.full(32, 60, dtype=np.int32)})
+    temps = oracle.log_temperatures()
+    full = ftlm.thermo(16, recs, temps, 1.0)
+    for i in (0, 1, 99, 150, 199):
+        one = ftlm.thermo(16, recs, temps[i:i + 1], 1.0)
+        for key in ("E", "C", "chi", "lnZ"):
+            assert one[key][0] == full[key][i], (key, i)
+
+
 def test_thermo_matches_oracle(ftlm):
     n = 10
     bonds = graphs.random_cluster(n, np.random.default_rng(3))
