@@ -197,14 +197,10 @@ void ftlm_server::retire(const std::shared_ptr<Request>& r) {
     int rc = job_collect(r->job, M, a.data(), b.data(), steps.data(), stream);
     if (rc == FTLM_OK) {
         r->steps = 0;
-        for (int c = 0; c < R; ++c) {
-            const int k = steps[size_t(c)];
-            r->steps += k;
-            if (k < 1 || ftlm_ritz(k, &a[size_t(c) * M], &b[size_t(c) * M], &th[size_t(c) * M], &w[size_t(c) * M])) {
-                rc = FTLM_E_INVALID;
-                break;
-            }
-        }
+        for (int c = 0; c < R; ++c) r->steps += steps[size_t(c)];
+        // every chain solved as ftlm_ritz solves it, on host threads
+        if (ftlm_ritz_batch(R, M, steps.data(), a.data(), b.data(), th.data(), w.data()) != FTLM_OK)
+            rc = FTLM_E_INVALID;
     }
     if (rc == FTLM_OK && r->nT > 0) {
         ftlm_sector_result sr{};
