@@ -39,9 +39,9 @@ LAUNCH_WIDTHS_F32 = (1, 2, 4, 8, 10, 12, 16, 20, 32)
 # copy (profiles/hv_lanczos_n30_r20_counters.md). They describe the kernel
 # sources with this hash and are dropped otherwise.
 KERNEL_SOURCES = ["layout.hpp", "device.hpp", "kernels.hpp", "rowloop.hpp", "hv_impl.hpp", "hv_f32.hip"]
-MEASURED_TRAFFIC = {"sources": "7318781b68d46eea", "bytes": {
-    "clt": {1: 19.11e9, 2: 34.76e9, 4: 67.57e9, 8: 126.29e9, 10: 166.25e9, 12: 206.54e9, 16: 280.07e9, 20: 378.51e9},
-    "cr": {1: 12.81e9, 2: 26.94e9, 4: 55.15e9, 8: 117.11e9, 10: 154.75e9, 12: 192.33e9, 16: 250.61e9, 20: 317.46e9}}}
+MEASURED_TRAFFIC = {"sources": "c078a2c571d64cdc", "bytes": {
+    "clt": {1: 20.54e9, 2: 34.93e9, 4: 67.68e9, 8: 128.22e9, 10: 166.94e9, 12: 200.07e9, 16: 279.89e9, 20: 378.8e9},
+    "cr": {1: 12.83e9, 2: 26.93e9, 4: 55.24e9, 8: 117.09e9, 10: 155.24e9, 12: 192.96e9, 16: 250.5e9, 20: 318.03e9}}}
 
 
 def kernel_source_hash():

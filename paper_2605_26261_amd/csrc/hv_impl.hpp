@@ -89,8 +89,10 @@ struct GatherVisitor {
     __device__ __forceinline__ void par(int) {}
     // CLT: a group of kGroup consecutive bonds: the rows of the antiparallel
     // ones are loaded together (lanes whose bond is parallel load nothing),
-    // then accumulated with weight J_b / 2 or zero.
-    static constexpr int kGroup = VB >= 16 ? 2 : 4;
+    // then accumulated with weight J_b / 2 or zero. Sizes measured per width
+    // (Lanczos step at N = 30): 8 at one column (9.0 -> 8.3 ms against 4),
+    // 6 at 8 columns, 3 at 12, 2 from 16 up, 4 elsewhere.
+    static constexpr int kGroup = VB == 1 ? 8 : VB == 8 ? 6 : VB == 12 ? 3 : VB >= 16 ? 2 : 4;
     // CR: bonds of one lower site in groups of kSiteGroup, two groups deep
     // (issue / finish below) for blocks of up to 20 columns; wider blocks take
     // one bond at a time (flip / par).
