@@ -90,6 +90,8 @@ def lib():
         L.orc_splitmix64_output.argtypes = [u64, u64]
         L.orc_start_vector.restype = None
         L.orc_start_vector.argtypes = [u64, i32, u64, i32, u64, vp]
+        L.orc_moments_stream.restype = None
+        L.orc_moments_stream.argtypes = [i32, i32, i32, vp, vp, vp, u64, u64, i32, i32, vp]
         _lib = L
     return _lib
 
@@ -231,6 +233,27 @@ def hv_rows_stream(n_sites, n_up, bonds, seed, r, dist, rows):
     lib().orc_hv_rows_stream(n_sites, n_up, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), seed, r, dist, _ptr(rows),
                              rows.size, _ptr(y))
     return y
+
+
+def first_step_moments(n_sites, n_up, bonds, seed, r0, R, dist):
+    """<x|x>, <x|H|x> and <Hx|Hx> of the unnormalized start vectors of samples
+    r0 .. r0 + R - 1 over the whole sector, entries generated on demand.
+    Returns a [R][3] array."""
+    bi, bj, J = _bonds(bonds)
+    out = np.empty((R, 3), dtype=np.float64)
+    lib().orc_moments_stream(n_sites, n_up, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), seed, r0, R, dist,
+                             _ptr(out))
+    return out
+
+
+def first_step(moments):
+    """alpha_1 and beta_1 of Lanczos from the normalized start vector, from
+    its moments (alpha_1 = <x|H|x>/<x|x>, alpha_1^2 + beta_1^2 =
+    <Hx|Hx>/<x|x>)."""
+    m = np.asarray(moments, dtype=np.float64)
+    a = m[:, 1] / m[:, 0]
+    b = np.sqrt(m[:, 2] / m[:, 0] - a * a)
+    return a, b
 
 
 def start_vector(seed, n_up, r, dist, dim, normalize=True):

@@ -383,3 +383,66 @@ void orc_hv_rows_stream(int n_sites, int n_up, int n_bonds, const int32_t* bi, c
         y[k] = acc;
     }
 }
+
+/* Next sector label after x in ascending order: the smallest integer above x
+ * with the same number of set bits. With c the lowest set bit of x, adding c
+ * carries the lowest run of ones one place up; the ones the carry removed,
+ * less one, go back to the bottom. */
+static uint64_t next_label(uint64_t x) {
+    uint64_t c = x & (~x + 1);
+    uint64_t r = x + c;
+    return r | (((x ^ r) >> 2) / c);
+}
+
+/* First-step moments of the start vectors of samples r0 .. r0 + R - 1 over
+ * the whole sector, with every entry generated on demand (no stored vector):
+ * out[3 r] = <x|x>, out[3 r + 1] = <x|H|x>, out[3 r + 2] = <Hx|Hx> for the
+ * unnormalized x of sample r0 + r. For the normalized start vector these give
+ * alpha_1 = <x|H|x> / <x|x> and alpha_1^2 + beta_1^2 = <Hx|Hx> / <x|x> (the
+ * first Lanczos step, Sec. 2). Rows are walked in chunks of 2^16 in
+ * ascending label order; each chunk's sums are added in chunk order, so the
+ * result does not depend on the thread count. 1 <= R <= 8. */
+void orc_moments_stream(int n_sites, int n_up, int n_bonds, const int32_t* bi, const int32_t* bj,
+                        const double* J, uint64_t seed, uint64_t r0, int R, int dist, double* out) {
+    const uint64_t dim = orc_sector_dim(n_sites, n_up);
+    const uint64_t chunk = (uint64_t)1 << 16;
+    const uint64_t nchunks = (dim + chunk - 1) / chunk;
+    uint64_t key[8];
+    for (int r = 0; r < R; ++r) key[r] = orc_stream_key(seed, n_up, r0 + (uint64_t)r);
+    double* part = (double*)calloc((size_t)nchunks * 3 * (size_t)R, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t ci = 0; ci < (int64_t)nchunks; ++ci) {
+        uint64_t t0 = (uint64_t)ci * chunk;
+        uint64_t t1 = t0 + chunk < dim ? t0 + chunk : dim;
+        uint64_t n = orc_unrank(n_sites, n_up, t0);
+        double* p = part + (size_t)ci * 3 * (size_t)R;
+        for (uint64_t t = t0; t < t1; ++t) {
+            double xt[8], y[8];
+            for (int r = 0; r < R; ++r) {
+                xt[r] = stream_entry(key[r], r0 + (uint64_t)r, dist, t);
+                y[r] = 0.0;
+            }
+            for (int b = 0; b < n_bonds; ++b) {
+                int up_i = (int)((n >> bi[b]) & 1u), up_j = (int)((n >> bj[b]) & 1u);
+                double mi = up_i ? 0.5 : -0.5, mj = up_j ? 0.5 : -0.5;
+                for (int r = 0; r < R; ++r) y[r] += J[b] * mi * mj * xt[r];
+                if (up_i != up_j) {
+                    uint64_t partner = n ^ (((uint64_t)1 << bi[b]) | ((uint64_t)1 << bj[b]));
+                    uint64_t idx = orc_rank(n_sites, n_up, partner);
+                    for (int r = 0; r < R; ++r)
+                        y[r] += 0.5 * J[b] * stream_entry(key[r], r0 + (uint64_t)r, dist, idx);
+                }
+            }
+            for (int r = 0; r < R; ++r) {
+                p[3 * r] += xt[r] * xt[r];
+                p[3 * r + 1] += xt[r] * y[r];
+                p[3 * r + 2] += y[r] * y[r];
+            }
+            if (t + 1 < t1) n = next_label(n);
+        }
+    }
+    for (int k = 0; k < 3 * R; ++k) out[k] = 0.0;
+    for (uint64_t ci = 0; ci < nchunks; ++ci)
+        for (int k = 0; k < 3 * R; ++k) out[k] += part[ci * 3 * (uint64_t)R + (uint64_t)k];
+    free(part);
+}

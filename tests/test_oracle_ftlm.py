@@ -75,6 +75,25 @@ def test_lanczos_first_coefficients():
     assert abs(a[0] ** 2 + b[0] ** 2 - hq @ hq) < 1e-10
 
 
+@pytest.mark.parametrize("n,n_up,dist", [(10, 5, oracle.GAUSS), (12, 6, oracle.PM1), (11, 7, oracle.GAUSS)])
+def test_first_step_moments_against_dense_h(n, n_up, dist):
+    # the streamed moments (labels walked by next-combination, entries and
+    # partner indices generated on demand) against the dense Kronecker-product
+    # H restricted to the sector and the stored start vectors
+    bonds = graphs.j1j2_ring(n, 1.0, 0.45)
+    h, _ = ed.sector_block(ed.hamiltonian(n, bonds), n, n_up)
+    m = oracle.first_step_moments(n, n_up, bonds, 7, 2, 3, dist)
+    for r in range(3):
+        x = oracle.start_vector(7, n_up, 2 + r, dist, h.shape[0], normalize=False)
+        hx = h @ x
+        np.testing.assert_allclose(m[r], [x @ x, x @ hx, hx @ hx], rtol=1e-12)
+    a, b = oracle.first_step(m)
+    for r in range(3):
+        q = oracle.start_vector(7, n_up, 2 + r, dist, h.shape[0])
+        al, be, _ = oracle.lanczos(lambda v: h @ v, q, 2)
+        assert abs(a[r] - al[0]) < 1e-12 and abs(b[r] - be[0]) < 1e-11
+
+
 @pytest.mark.parametrize("m", [4, 12, 40])
 def test_gauss_quadrature_moments(m):
     # sum_k w_k theta_k^p = <r|H^p|r> for p <= 2m - 1 (checked to p = 4)
