@@ -54,6 +54,8 @@ extern "C" {
 #define FTLM_E_DEVICE (-4)   /* a HIP runtime error; the message names it */
 #define FTLM_E_AGAIN (-5)    /* server: the result is not ready yet */
 #define FTLM_E_REJECTED (-6) /* server: the request can never fit the arena */
+#define FTLM_E_NUMERIC (-7)  /* a Lanczos chain met a NaN or infinite alpha or beta; it was
+                                stopped at that step, the outputs are still written */
 
 /* ---- enumerations ------------------------------------------------------ */
 #define FTLM_CLT 0   /* compressed lookup table indexing (Sec. 2, Eqs. 18-21, Alg. 2) */
@@ -67,9 +69,6 @@ extern "C" {
 #define FTLM_UNIT 2  /* the unit vector e_r (exact trace when R = D) */
 
 #define FTLM_NONE UINT64_MAX
-
-#define FTLM_SPLIT_OFF 0 /* one-pass H.x (the default) */
-#define FTLM_SPLIT_ON 1  /* two-pass H.x whenever the graph has a split and D >= 2048 */
 
 typedef struct ftlm_graph ftlm_graph;
 typedef struct ftlm_sector ftlm_sector;
@@ -95,31 +94,16 @@ void ftlm_graph_destroy(ftlm_graph* g);
 int ftlm_graph_n_sites(const ftlm_graph* g);
 int ftlm_graph_n_bonds(const ftlm_graph* g);
 
-/* ftlm_graph_split: the two-pass site split chosen for the graph's H.x (an
- * implementation choice, not from the paper). The row-wise gather of Eq. 12
- * reads the partner row of every antiparallel bond; in the increasing-label
- * order of the sector a bond touching a high site sends the partner far from
- * its row, so a single pass re-reads x from HBM. The library labels the sites
- * so that [0, c) | [c, s) | [s, N) separates the bonds: every bond lies inside
- * [0, s) or joins [s, N) to [0, c) or to itself. A first pass then applies the
- * bonds inside [0, s) to rows in index order, and a second pass the others to
- * blocks of rows that share their digits on [c, s); every block holds its rows'
- * partners and fits in on-chip cache. site_order (host int32[N], may be null)
- * receives the position of each of the caller's sites in that labelling; *c
- * and *s receive the split (both 0 when the graph has none). Relabelling a
- * graph with site_order gives a graph whose split keeps its own labels. */
-int ftlm_graph_split(const ftlm_graph* g, int32_t* site_order, int32_t* c, int32_t* s);
-
-/* ftlm_set_split_policy: FTLM_SPLIT_OFF (default) or FTLM_SPLIT_ON, for the
- * H.x launches and Lanczos runs set up after the call (process-wide; the
- * choice changes the order of floating-point sums, not the result beyond
- * rounding). On gfx950 the one-pass form measured faster on the N = 30
- * workload: its time follows the number of scattered row fetches, which the
- * split does not reduce, rather than the HBM re-reads it removes. */
-int ftlm_set_split_policy(int policy);
-
 /* ---- S^z sector -------------------------------------------------------
- * ftlm_sector_table_bytes: device bytes the sector tables need. Both modes
+ * ftlm_sector_info: the sector's dimension D = C(N, n_up) (Eq. 15 at
+ * s = 1/2; Eq. 17 fixes n_up = N/2 + M) and its weight in the thermal sums
+ * of Eqs. 6-9: 1 for M = 0 and 2 otherwise, because the sectors +M and -M
+ * have the same spectrum (Sec. 2, which restricts the runs to M >= 0). Either
+ * output may be NULL. Errors: FTLM_E_RANGE for N outside [1, 64],
+ * FTLM_E_INVALID for n_up outside [0, N]. */
+int ftlm_sector_info(int n_sites, int n_up, uint64_t* dim, double* mult);
+
+/* ftlm_sector_table_bytes: device bytes the sector tables need. Both modes
  * hold a binomial table C(p, k) (the cumulative dimension table D_c(p, A, 1)
  * of Eq. 16 at s = 1/2, a few KB). FTLM_CLT adds the sorted basis (uint32
  * per state, N <= 32) and the compressed lookup table: one {mask, prefix}
@@ -178,10 +162,7 @@ int ftlm_neighbors(const ftlm_sector* s, const ftlm_graph* g, uint64_t t0, uint6
  * state n_t as
  *   y[t] = sum_b J_b s^z_i s^z_j x[t] + sum_{b antiparallel} (J_b / 2) x[idx(n_t ^ mask_b)]
  * with s^z_i s^z_j = +-1/4, no atomics. dtype FTLM_F32 accumulates each row in
- * FP32, FTLM_F64 in FP64. x and y must not overlap. 1 <= nvec <= 64. When the
- * graph's split keeps the caller's labels (ftlm_graph_split) and the policy
- * allows (FTLM_SPLIT_ON), the product runs in two passes (the second adds
- * into y). */
+ * FP32, FTLM_F64 in FP64. x and y must not overlap. 1 <= nvec <= 64. */
 int ftlm_hv(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, void* y_dev, int nvec,
             int dtype, void* stream);
 
@@ -222,10 +203,9 @@ int ftlm_lanczos_workspace_bytes(const ftlm_sector* s, int R, int dtype, size_t*
  * min(M, D) or beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}), with eps =
  * 1e-6 (FP32) or 1e-12 (FP64). Outputs (host, synchronizes): alpha_host and
  * beta_host [R][M] (row r holds chain r; entries past steps_host[r] are 0),
- * steps_host[R]. 1 <= R <= 64, 1 <= M <= 4096. With the two-pass H.x the
- * chains run in the split's site labelling; start-vector entries stay keyed
- * by the state's index in the caller's labels, so the chains are the same up
- * to rounding. */
+ * steps_host[R]. 1 <= R <= 64, 1 <= M <= 4096. A chain whose alpha_k or
+ * beta_k comes out NaN or infinite stops at that step and the call returns
+ * FTLM_E_NUMERIC after writing every output. */
 int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint64_t r0, int R,
                  int M, int dist, int dtype, void* work_dev, size_t work_bytes, double* alpha_host,
                  double* beta_host, int32_t* steps_host, void* stream);
@@ -242,7 +222,7 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
  * all R chains run as floor(R / B) batches of B and one of R mod B, each
  * batch priced as the sum of its column chunks (the launch widths
  * ftlm_lanczos cuts it into). Results are cached per (N, n_up,
- * bonds, mode, dtype, R, split policy) for the life of the process; the file named by the
+ * bonds, mode, dtype, R) for the life of the process; the file named by the
  * environment variable FTLM_AUTOTUNE_CACHE, when set, is read and appended
  * (one "key batch ms" line per entry). The workgroup grid is not tuned: it
  * fixes the FP64 reduction order, so results never depend on the choice. */

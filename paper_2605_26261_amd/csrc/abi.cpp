@@ -62,7 +62,6 @@ int ftlm_graph_create(int n_sites, int n_bonds, const int32_t* bi, const int32_t
         jsum += g->J[b];
     }
     g->table = make_bond_table(n_sites, g->bi, g->bj, g->J, orig, jsum);
-    plan_split(g);
     *out = g;
     return ok();
 }
@@ -71,23 +70,15 @@ void ftlm_graph_destroy(ftlm_graph* g) { delete g; }
 int ftlm_graph_n_sites(const ftlm_graph* g) { return g ? g->n_sites : 0; }
 int ftlm_graph_n_bonds(const ftlm_graph* g) { return g ? int(g->bi.size()) : 0; }
 
-int ftlm_graph_split(const ftlm_graph* g, int32_t* site_order, int32_t* c, int32_t* s) {
-    if (!g || !c || !s) return fail(FTLM_E_INVALID, "null argument");
-    *c = g->split ? g->split_c : 0;
-    *s = g->split ? g->split_s : 0;
-    if (site_order)
-        for (int k = 0; k < g->n_sites; ++k) site_order[k] = g->split ? g->split_site[size_t(k)] : k;
-    return ok();
-}
-
-int ftlm_set_split_policy(int policy) {
-    if (policy != FTLM_SPLIT_OFF && policy != FTLM_SPLIT_ON)
-        return fail(FTLM_E_INVALID, "split policy %d", policy);
-    g_split_policy = policy;
-    return ok();
-}
-
 // ---- sector ---------------------------------------------------------------------
+int ftlm_sector_info(int n_sites, int n_up, uint64_t* dim, double* mult) {
+    if (n_sites < 1 || n_sites > kMaxSites) return fail(FTLM_E_RANGE, "n_sites %d not in [1, %d]", n_sites, kMaxSites);
+    if (n_up < 0 || n_up > n_sites) return fail(FTLM_E_INVALID, "n_up %d not in [0, %d]", n_up, n_sites);
+    if (dim) *dim = binom_u64(n_sites, n_up);
+    if (mult) *mult = sector_multiplicity(n_sites, n_up);
+    return ok();
+}
+
 int ftlm_sector_table_bytes(int n_sites, int n_up, int mode, size_t* bytes) {
     if (!bytes) return fail(FTLM_E_INVALID, "null argument");
     if (mode != FTLM_CLT && mode != FTLM_CR) return fail(FTLM_E_INVALID, "mode %d is not FTLM_CLT/FTLM_CR", mode);
@@ -216,20 +207,11 @@ int ftlm_hv_rows(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, v
     h.nrows = uint32_t(nrows);
     h.dtype = dtype;
     h.grid = int(rows_grid(uint32_t(nrows)));
-    // two passes when the split keeps the caller's labels (whole product only)
-    const bool split = row0 == 0 && nrows == s->dim && g->split_identity && use_split(g, s->dim, nvec, dtype);
-    h.split_c = g->split_c;
-    h.split_s = g->split_s;
     for (auto [col, vb] : column_chunks(nvec, uint64_t(nvec), dtype, {x_dev, y_dev})) {
         h.col0 = uint32_t(col);
         h.vb = vb;
         HvTimer timer(st);
-        if (split) {
-            HIP_CHECK(launch_hv(s->dev, g->p1, h, st));
-            HIP_CHECK(launch_hv_split(s->dev, g->p2, h, st));
-        } else {
-            HIP_CHECK(launch_hv(s->dev, g->table, h, st));
-        }
+        HIP_CHECK(launch_hv(s->dev, g->table, h, st));
     }
     return ok();
 }
@@ -335,12 +317,11 @@ struct TuneCache {
     std::map<std::string, std::pair<int, double>> entries;
 } g_tune;
 
-// "_c2": the candidate set and cost model; a cache file written under an
-// older one is not reused.
+// "_c3": the candidate set, cost model and kernel set; a cache file written
+// under an older one is not reused.
 std::string tune_key(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype) {
     std::string k = "N" + std::to_string(s->n_sites) + "_u" + std::to_string(s->n_up) + "_m" +
-                    std::to_string(s->mode) + "_t" + std::to_string(dtype) + "_R" + std::to_string(R) + "_p" +
-                    std::to_string(g_split_policy) + "_c2_b";
+                    std::to_string(s->mode) + "_t" + std::to_string(dtype) + "_R" + std::to_string(R) + "_c3_b";
     // the bond structure, so that two graphs with the same size do not share entries
     uint64_t h = 1469598103934665603ull;
     for (size_t b = 0; b < g->bi.size(); ++b) {

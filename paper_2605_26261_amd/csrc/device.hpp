@@ -285,22 +285,4 @@ __device__ __forceinline__ L visit_row(uint32_t t, int n_up, const BondTable& B,
     }
 }
 
-// Visits the row with label n (a sector member): returns its index t (Alg. 2
-// in CLT mode, Alg. 1 in CR mode) and reports its bonds as visit_row does.
-template <typename L, int MODE, typename V>
-__device__ __forceinline__ uint32_t visit_label(L n, int n_up, const BondTable& B, Binom C,
-                                                const CltEntry* __restrict__ clt, uint32_t* ylds, V& v) {
-    if constexpr (MODE == kModeClt) {
-        const uint32_t n32 = uint32_t(n);
-        const CltEntry e = clt_entry(clt, n32 >> 5);
-        const uint32_t t = e.prefix + __popc(e.mask & ((1u << (n32 & 31u)) - 1u));
-        clt_bonds(n32, B, clt, v);
-        return t;
-    } else {
-        const uint32_t t = cr_rank<L>(n, B.n_sites, n_up, C);
-        cr_bonds<L, true>(t, n, n_up, B, C, ylds, v);
-        return t;
-    }
-}
-
 }  // namespace ftlm

@@ -128,8 +128,7 @@ size_t layout_state(uint64_t dim, int R, int dtype, size_t off, SectorState& st)
 
 // Fills job.secs for sectors whose tables are described by `devs` and whose
 // state sits at `states` inside `base`. Each graph contributes its bond table
-// in the caller's labels and its two split tables; a sector takes the split
-// tables when use_split() says so. The descriptor array goes to `dev_secs`
+// in the caller's labels. The descriptor array goes to `dev_secs`
 // (device). Blocks: each sector gets rows_grid(D) blocks starting at a
 // multiple of 8.
 void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::vector<SectorState>& states,
@@ -147,8 +146,6 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
         const ftlm_graph* g = graphs[gi];
         const BondTable zero{};
         job.bonds.push_back(g ? g->table : zero);
-        job.bonds.push_back(g && g->split ? g->p1 : zero);
-        job.bonds.push_back(g && g->split ? g->p2 : zero);
         for (int k = 0; k < kTablesPerGraph; ++k) job.dev_bonds.push_back(dev_tables[gi] + k);
     }
     job.secs.assign(devs.size(), SecWork{});
@@ -156,12 +153,10 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
     uint32_t block = 0;
     size_t lds = 0;
     job.max_steps = 0;
-    job.any_split = false;
     for (size_t i = 0; i < devs.size(); ++i) {
         SecWork& w = job.secs[i];
         const SectorState& st = states[i];
         const int gi = graph_of[i];
-        const ftlm_graph* g = graphs[size_t(gi)];
         w.S = devs[i];
         w.bonds = dev_tables[size_t(gi)];
         w.u[0] = at<void>(base, st.u0);
@@ -180,17 +175,6 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
         w.m_eff = int(std::min<uint64_t>(uint64_t(M), devs[i].dim));
         job.max_steps = std::max(job.max_steps, w.m_eff);
         lds = std::max(lds, hv_lds_bytes(devs[i]));
-        if (use_split(g, devs[i].dim, R, dtype)) {
-            w.split = 1;
-            w.split_c = g->split_c;
-            w.split_s = g->split_s;
-            w.bonds = dev_tables[size_t(gi)] + 1;
-            w.bonds2 = dev_tables[size_t(gi)] + 2;
-            w.relabel = g->split_identity ? 0 : 1;
-            for (int k = 0; k < g->n_sites; ++k) w.user_site[k] = uint8_t(g->user_site[size_t(k)]);
-            lds = std::max(lds, hv_split_lds_bytes(devs[i]));
-            job.any_split = true;
-        }
     }
     job.grid = int(block);
     job.lds = lds;
@@ -237,10 +221,8 @@ int job_steps(const LanczosJob& job, hipStream_t st, bool timed, int nsteps) {
             if (timed) {
                 HvTimer timer(st);
                 HIP_CHECK(launch_hv_lanczos(a, job.lds, st));
-                if (job.any_split) HIP_CHECK(launch_hv_split_lanczos(a, job.lds, st));
             } else {
                 HIP_CHECK(launch_hv_lanczos(a, job.lds, st));
-                if (job.any_split) HIP_CHECK(launch_hv_split_lanczos(a, job.lds, st));
             }
             HIP_CHECK(launch_update(a, st));
         }
@@ -263,9 +245,11 @@ int job_collect(const LanczosJob& job, int M, double* alpha_host, double* beta_h
         HIP_CHECK(hipMemcpyAsync(ch.data() + size_t(s) * R, w.chains, R * sizeof(Chain), hipMemcpyDeviceToHost, st));
     }
     HIP_CHECK(hipStreamSynchronize(st));
+    int faulty = -1;
     for (int s = 0; s < job.nsec; ++s) {
         for (size_t r = 0; r < R; ++r) {
             const Chain& c = ch[size_t(s) * R + r];
+            if (c.fault && faulty < 0) faulty = int(size_t(s) * R + r);
             const size_t row = size_t(s) * R + r;
             steps_host[row] = c.steps;
             for (int k = 0; k < M; ++k) {
@@ -275,6 +259,9 @@ int job_collect(const LanczosJob& job, int M, double* alpha_host, double* beta_h
             }
         }
     }
+    if (faulty >= 0)
+        return fail(FTLM_E_NUMERIC, "chain %d of sector %d stopped on a non-finite alpha or beta at step %d",
+                    faulty % int(R), faulty / int(R), ch[size_t(faulty)].steps);
     return FTLM_OK;
 }
 

@@ -20,15 +20,6 @@ struct ftlm_graph {
     int n_input = 0;           // bonds as given (before merging)
     std::vector<int> merged_of_input;
     ftlm::BondTable table{};   // in the caller's site labels
-    // Two-pass split (split.cpp): sites relabelled so that [0, split_c) |
-    // [split_c, split_s) | [split_s, N) separates the bonds; p1 holds the bonds
-    // inside [0, split_s) (and sum_b J_b / 4 over all bonds), p2 the others.
-    bool split = false;
-    bool split_identity = true;
-    int split_c = 0, split_s = 0;
-    std::vector<int> split_site;  // [caller's site] -> site in the split order
-    std::vector<int> user_site;   // [site in the split order] -> caller's site
-    ftlm::BondTable p1{}, p2{};
 };
 
 struct ftlm_sector {
@@ -57,6 +48,10 @@ int ok();
 
 uint64_t binom_u64(int n, int k);
 
+// Weight of a sector in the thermal sums: the sectors +M and -M have the
+// same spectrum (Sec. 2), so a sector with M != 0 stands for both.
+inline double sector_multiplicity(int n_sites, int n_up) { return 2 * n_up == n_sites ? 1.0 : 2.0; }
+
 // Two timing events destroyed on every exit path.
 struct EventPair {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -73,13 +68,10 @@ struct EventPair {
     }
 };
 
-// Bond tables and the two-pass split (split.cpp).
+// Bond tables of the row kernels (bonds.cpp).
 BondTable make_bond_table(int n_sites, const std::vector<int>& lo, const std::vector<int>& hi,
                           const std::vector<double>& J, const std::vector<int>& orig, double jsum_all);
-void plan_split(ftlm_graph* g);
-extern int g_split_policy;
-bool use_split(const ftlm_graph* g, uint64_t dim, int R, int dtype);
-constexpr int kTablesPerGraph = 3;  // caller's labels, split pass 1, split pass 2
+constexpr int kTablesPerGraph = 1;  // the graph's bond table
 uint64_t stream_key(uint64_t seed, int n_up, uint64_t r);
 
 // ---- stats -------------------------------------------------------------------
@@ -146,7 +138,6 @@ struct LanczosJob {
     std::vector<BondTable*> dev_bonds;   // where each copy goes
     std::vector<std::pair<int, int>> chunks;
     int max_steps = 0;                   // largest m_eff over the sectors
-    bool any_split = false;              // some sector runs the two-pass H.x
 
     LanczosLaunch launch() const {
         LanczosLaunch a{};

@@ -3,6 +3,6 @@
 
 namespace ftlm {
 template hipError_t launch_hv_typed<float>(const SectorDev&, const BondTable&, const HvLaunch&, hipStream_t);
-template hipError_t launch_lanczos_typed<float, false>(int, int, const LanczosLaunch&, size_t,
+template hipError_t launch_lanczos_typed<float>(int, int, const LanczosLaunch&, size_t,
                                                 hipStream_t);
 }  // namespace ftlm

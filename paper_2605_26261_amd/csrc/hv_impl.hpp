@@ -231,7 +231,7 @@ __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, 
 #pragma unroll
             for (int c = 0; c < VB; ++c) out[c] = diag * xt[c] + acc[c];
             T* yrow = y + uint64_t(r) * ld + col0;
-            if constexpr (EPI == kEpiLanczos || EPI == kEpiLanczosPart) {
+            if constexpr (EPI == kEpiLanczos) {
                 T z[VB];
                 if (!first) {
                     load_row<T, VB>(yrow, z);
@@ -343,172 +343,8 @@ __global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(LanczosLaunch a) {
     __syncthreads();
     const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
     T* y = static_cast<T*>(sw.u[step & 1]);
-    if (sw.split) {
-        // first pass of a two-pass step: the bonds inside [0, split_s)
-        hv_body<L, MODE, T, VB, kEpiLanczosPart>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, ab,
-                                                  step == 1, nullptr);
-        return;
-    }
     hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, ab, step == 1,
                                           wsum);
-    alpha_tail<VB>(sw, a, wsum, lds.red, local, &flag);
-}
-
-// ---- two-pass H.x --------------------------------------------------------------
-// The sites are split as [0, c) | [c, s) | [s, N): every bond lies inside
-// [0, s) (first pass) or touches [s, N) with its other site in [0, c) or
-// [s, N) (second pass). The first pass is the row kernel above over rows in
-// index order with the bonds inside [0, s): rows with equal digits on [s, N)
-// are contiguous, and those bonds keep a row inside that run. The second pass
-// groups its rows into blocks: a block fixes the digits of the middle sites
-// [c, s) (q of them up) and holds every sector label with those digits, in
-// increasing order; its rows are the C(P, n_up - q) configurations of the
-// P = N - (s - c) sites [0, c) and [s, N), and the second-pass bonds map a
-// block onto itself. Rows of a block with equal digits on [c, N) have
-// consecutive indices, so the block's rows of x and y come in runs.
-//
-// Blocks are numbered by q, then by the rank j of their middle digits among
-// the (s - c)-digit labels with q ones; block number b goes to XCD b mod 8,
-// whose workgroups walk the tiles of its blocks in order, so a block's rows
-// of x stay in one XCD's L2 while they are gathered.
-struct SplitTile {
-    uint64_t mid;   // middle digits
-    int q;          // ones among them
-    uint32_t v0;    // first row of the tile inside the block
-    uint32_t rows;  // rows of the block
-};
-
-struct SplitSched {
-    int c, s, n_up, wm, P, qlo, qhi;
-    Binom C;
-
-    __device__ __forceinline__ SplitSched(int c_, int s_, int n_sites, int n_up_, Binom C_)
-        : c(c_), s(s_), n_up(n_up_), wm(s_ - c_), P(n_sites - (s_ - c_)), C(C_) {
-        qlo = n_up - P > 0 ? n_up - P : 0;
-        qhi = wm < n_up ? wm : n_up;
-    }
-
-    // Walks the classes q for XCD x; with `want` < total tiles of x, stops at
-    // the tile of that local number. Returns the XCD's tile count.
-    __device__ __forceinline__ uint32_t walk(uint32_t x, uint32_t want, SplitTile* out) const {
-        uint32_t pre = 0, base8 = 0;
-        for (int q = qlo; q <= qhi; ++q) {
-            const uint32_t nq = C(wm, q);               // blocks of the class (< 2^32: nq * rows <= D)
-            const uint32_t rows = C(P, n_up - q);
-            const uint32_t tiles = (rows + kBlock - 1) / kBlock;
-            const uint32_t first = (x - base8) & 7u;    // first j of the class on XCD x
-            const uint32_t cnt = first < nq ? (nq - first + 7u) / 8u : 0u;
-            const uint32_t here = cnt * tiles;
-            if (out && want >= pre && want < pre + here) {
-                const uint32_t rem = want - pre;
-                const uint32_t i = rem / tiles;
-                const uint32_t j = first + 8u * i;
-                out->mid = cr_unrank<uint64_t>(j, wm, q, C);
-                out->q = q;
-                out->v0 = (rem - i * tiles) * kBlock;
-                out->rows = rows;
-                return 0;
-            }
-            pre += here;
-            base8 = (base8 + nq) & 7u;
-        }
-        return pre;
-    }
-};
-
-// Second pass over the tiles of block `bid` of a (sub-)grid of G blocks (G a
-// multiple of 8): y[t] += (H_2 x)[t] (plain), or, in the Lanczos epilogue,
-// w[t] += hv_a (H_2 u_k)[t] on top of the first pass's
-// w = hv_a (H_1 u_k) - hv_b u_{k-1}, folding u_k[t] w[t] into the per-wave
-// FP64 sums wsum. H_2 holds the second-pass bonds; their diagonal share is
-// -J_b / 2 for each antiparallel one (the first pass added sum_b J_b / 4 over
-// every bond).
-template <typename L, int MODE, typename T, int VB, int EPI>
-__device__ __forceinline__ void hv_split_body(const SectorDev& S, const BondTable& B2, const HvLds& lds, int c,
-                                              int s, const T* __restrict__ x, T* __restrict__ y, uint64_t ld,
-                                              uint32_t col0, uint32_t bid, uint32_t G, const T* ab,
-                                              double* wsum) {
-    const Binom C{lds.binom, S.bw};
-    const int wave = threadIdx.x >> 6;
-    const SplitSched sc(c, s, S.n_sites, S.n_up, C);
-    const uint32_t xcd = bid & 7u, slot = bid >> 3, per = G >> 3;
-    const uint32_t total = sc.walk(xcd, 0, nullptr);
-    const L lowmask = (L(1) << c) - L(1);
-    for (uint32_t k = slot; k < total; k += per) {
-        SplitTile tl;
-        sc.walk(xcd, k, &tl);
-        const uint32_t v = tl.v0 + threadIdx.x;
-        const bool valid = v < tl.rows;
-        T xt[VB], out[VB];
-        if (valid) {
-            const L lam = cr_unrank<L>(v, sc.P, S.n_up - tl.q, C);
-            const L n = (lam & lowmask) | (L(tl.mid) << c) | ((lam >> c) << s);
-            T acc[VB];
-#pragma unroll
-            for (int i = 0; i < VB; ++i) acc[i] = T(0);
-            T anti = T(0);
-            GatherVisitor<T, VB> vis{x, ld, col0, S.dim - 1, B2, acc, anti};
-            uint32_t t = visit_label<L, MODE>(n, S.n_up, B2, C, S.clt, lds.ylds, vis);
-            t = t < S.dim ? t : S.dim - 1;
-            load_row<T, VB>(x + uint64_t(t) * ld + col0, xt);
-            T* yrow = y + uint64_t(t) * ld + col0;
-            T z[VB];
-            load_row<T, VB>(yrow, z);
-#pragma unroll
-            for (int i = 0; i < VB; ++i) {
-                const T h = acc[i] - anti * xt[i];
-                if constexpr (EPI == kEpiLanczos) {
-                    out[i] = z[i] + ab[i] * h;
-                } else {
-                    out[i] = z[i] + h;
-                }
-            }
-            store_row<T, VB>(yrow, out);
-        }
-        if constexpr (EPI == kEpiLanczos) {
-            double p[VB];
-#pragma unroll
-            for (int i = 0; i < VB; ++i) p[i] = valid ? double(xt[i]) * double(out[i]) : 0.0;
-            wave_fold_columns<VB>(p, wsum + wave * VB);
-        }
-    }
-}
-
-template <typename L, int MODE, typename T, int VB>
-__global__ __launch_bounds__(kBlock) void hv_split_kernel(SectorDev S, BondTable B2, HvLaunch h) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const HvLds lds = hv_lds_setup<MODE, true>(smem, S);
-    hv_split_body<L, MODE, T, VB, kEpiPlain>(S, B2, lds, h.split_c, h.split_s, static_cast<const T*>(h.x),
-                                              static_cast<T*>(h.y), h.ld, h.col0, blockIdx.x, gridDim.x, nullptr,
-                                              nullptr);
-}
-
-// Second pass of a two-pass Lanczos step over the split sectors of the
-// launch, then alpha_k as in the one-pass kernel.
-template <typename L, int MODE, typename T, int VB>
-__global__ __launch_bounds__(kBlock) void hv_split_lanczos_kernel(LanczosLaunch a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int flag;
-    uint32_t local = 0;
-    const SecWork* secs = a.secs;
-    const int s = sector_of_block(secs, a.nsec, blockIdx.x, &local);
-    if (s < 0) return;
-    const SecWork& sw = secs[s];
-    if (!sw.split || sw.state[1] == 0) return;
-    const int step = sw.state[0];
-    const SectorDev S = sw.S;
-    __shared__ BondTable B2;
-    __shared__ T ab[2 * VB];
-    stage_bonds(B2, sw.bonds2);
-    stage_epilogue<T, VB>(ab, sw.chains + a.col0);
-    const HvLds lds = hv_lds_setup<MODE, true>(smem, S);
-    double* wsum = lds.red;
-    for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
-    __syncthreads();
-    const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
-    T* y = static_cast<T*>(sw.u[step & 1]);
-    hv_split_body<L, MODE, T, VB, kEpiLanczos>(S, B2, lds, sw.split_c, sw.split_s, x, y, a.ld,
-                                                a.col0, local, sw.G, ab, wsum);
     alpha_tail<VB>(sw, a, wsum, lds.red, local, &flag);
 }
 
@@ -535,24 +371,8 @@ hipError_t launch_hv_one(const SectorDev& s, const BondTable& B, const HvLaunch&
 }
 
 template <typename L, int MODE, typename T, int VB>
-hipError_t launch_split_one(const SectorDev& s, const BondTable& B2, const HvLaunch& h, hipStream_t st) {
-    const size_t lds = hv_split_lds_bytes(s);
-    auto kern = hv_split_kernel<L, MODE, T, VB>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3(unsigned(h.grid)), dim3(kBlock), lds, st, s, B2, h);
-    return hipGetLastError();
-}
-
-template <typename L, int MODE, typename T, int VB, bool SPLIT>
 hipError_t launch_lanczos_one(const LanczosLaunch& a, size_t lds, hipStream_t st) {
-    auto kern = [] {
-        if constexpr (SPLIT) return hv_split_lanczos_kernel<L, MODE, T, VB>;
-        else return hv_lanczos_kernel<L, MODE, T, VB>;
-    }();
+    auto kern = hv_lanczos_kernel<L, MODE, T, VB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -604,21 +424,11 @@ hipError_t launch_hv_typed(const SectorDev& s, const BondTable& B, const HvLaunc
 }
 
 template <typename T>
-hipError_t launch_split_typed(const SectorDev& s, const BondTable& B2, const HvLaunch& h, hipStream_t st) {
-    return with_mode(s.mode, s.n_sites, [&](auto l, auto m) {
-        using L = decltype(l);
-        return with_vb<T>(h.vb, [&](auto vb) {
-            return launch_split_one<L, decltype(m)::value, T, decltype(vb)::value>(s, B2, h, st);
-        });
-    });
-}
-
-template <typename T, bool SPLIT>
 hipError_t launch_lanczos_typed(int mode, int n_sites, const LanczosLaunch& a, size_t lds, hipStream_t st) {
     return with_mode(mode, n_sites, [&](auto l, auto m) {
         using L = decltype(l);
         return with_vb<T>(a.vb, [&](auto vb) {
-            return launch_lanczos_one<L, decltype(m)::value, T, decltype(vb)::value, SPLIT>(a, lds, st);
+            return launch_lanczos_one<L, decltype(m)::value, T, decltype(vb)::value>(a, lds, st);
         });
     });
 }

@@ -34,6 +34,8 @@ struct Chain {
     float hv_a_f, hv_b_f, up_f, pad_f;
     int32_t active;
     int32_t steps;
+    int32_t fault;     // 1 once alpha_k or beta_k came out NaN or infinite
+    int32_t pad_i;
 };
 
 // Sets the next-step scalars of a chain from its FP64 state.
@@ -56,9 +58,7 @@ struct SectorDev {
     const CltEntry* clt;     // [2^N / 32] (CLT mode)
 };
 
-// kEpiLanczosPart: the first pass of a two-pass step writes
-// w = hv_a (H_1 u_k) - hv_b u_{k-1} and leaves <u_k, w> to the second pass.
-enum Epilogue { kEpiPlain = 0, kEpiLanczos = 1, kEpiLanczosPart = 2 };
+enum Epilogue { kEpiPlain = 0, kEpiLanczos = 1 };
 
 // One plain multi-vector H.x launch over rows [row0, row0 + nrows) and the
 // columns [col0, col0 + vb) of [D][ld] blocks x (input) and y (output).
@@ -72,8 +72,6 @@ struct HvLaunch {
     int vb;
     int dtype;
     int grid;
-    int split_c;         // two-pass split of the sites (second pass only)
-    int split_s;
 };
 
 // One sector of a Lanczos launch (one sector, all sectors of a plan, or the
@@ -97,17 +95,6 @@ struct SecWork {
     uint32_t G;
     uint32_t block0;
     int32_t m_eff;       // min(M, D)
-    // Two-pass H.x (split != 0): `bonds` holds the bonds inside the sites
-    // [0, split_s) and `bonds2` those touching [split_s, N), in the split site
-    // order; start-vector entries are then keyed by the index of the state in
-    // the caller's site labels, site k of the split order being the caller's
-    // site user_site[k] (relabel != 0).
-    int32_t split;
-    int32_t split_c;
-    int32_t split_s;
-    int32_t relabel;
-    const BondTable* bonds2;
-    uint8_t user_site[kMaxSites];
 };
 
 // Kernel arguments of the Lanczos kernels over a list of sectors. Columns
@@ -128,9 +115,7 @@ struct LanczosLaunch {
 };
 
 hipError_t launch_hv(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st);
-hipError_t launch_hv_split(const SectorDev& s, const BondTable& B2, const HvLaunch& h, hipStream_t st);
 hipError_t launch_hv_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st);
-hipError_t launch_hv_split_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st);
 hipError_t launch_start(const LanczosLaunch& a, hipStream_t st);
 hipError_t launch_update(const LanczosLaunch& a, hipStream_t st);
 hipError_t launch_chain_init(const LanczosLaunch& a, hipStream_t st);
@@ -156,11 +141,6 @@ __host__ __device__ inline size_t hv_slab_lds_bytes(int n_sites, int mode) {
 }
 __host__ __device__ inline size_t hv_lds_bytes(const SectorDev& s) {
     return hv_red_bytes() + hv_binom_lds_bytes(s.n_sites, s.bw, s.mode) + hv_slab_lds_bytes(s.n_sites, s.mode);
-}
-// The second pass of a two-pass H.x enumerates its rows with the binomial
-// table in both indexing modes.
-__host__ __device__ inline size_t hv_split_lds_bytes(const SectorDev& s) {
-    return hv_red_bytes() + hv_binom_lds_bytes(s.n_sites, s.bw, kModeCr) + hv_slab_lds_bytes(s.n_sites, s.mode);
 }
 
 

@@ -9,17 +9,12 @@
 
 namespace ftlm {
 
-template <typename T, bool SPLIT>
+template <typename T>
 hipError_t launch_lanczos_typed(int, int, const LanczosLaunch&, size_t, hipStream_t);
 
 hipError_t launch_hv_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st) {
-    return a.dtype == 0 ? launch_lanczos_typed<float, false>(a.mode, a.n_sites, a, lds, st)
-                        : launch_lanczos_typed<double, false>(a.mode, a.n_sites, a, lds, st);
-}
-
-hipError_t launch_hv_split_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st) {
-    return a.dtype == 0 ? launch_lanczos_typed<float, true>(a.mode, a.n_sites, a, lds, st)
-                        : launch_lanczos_typed<double, true>(a.mode, a.n_sites, a, lds, st);
+    return a.dtype == 0 ? launch_lanczos_typed<float>(a.mode, a.n_sites, a, lds, st)
+                        : launch_lanczos_typed<double>(a.mode, a.n_sites, a, lds, st);
 }
 
 namespace {
@@ -66,20 +61,10 @@ __global__ __launch_bounds__(kBlock) void start_kernel(LanczosLaunch a) {
 #pragma unroll
     for (int c = 0; c < CB; ++c) part[c] = 0.0;
     const uint32_t ntiles = (dim + kBlock - 1) / kBlock;
-    const Binom C{sw.S.binom, sw.S.bw};
     for_each_tile(ntiles, local, sw.G, [&](uint32_t tile) {
         const uint32_t t = tile * kBlock + threadIdx.x;
         if (t >= dim) return;
-        // entry index: the row's index in the caller's site labels
-        uint64_t i = t;
-        if (sw.relabel) {
-            const int n_sites = sw.S.n_sites;
-            const uint64_t m = sw.S.mode == kModeClt ? uint64_t(sw.S.basis[t])
-                                                     : cr_unrank<uint64_t>(t, n_sites, sw.S.n_up, C);
-            uint64_t n = 0;
-            for (int k = 0; k < n_sites; ++k) n |= ((m >> k) & 1ull) << sw.user_site[k];
-            i = cr_rank<uint64_t>(n, n_sites, sw.S.n_up, C);
-        }
+        const uint64_t i = t;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             if (c < nc) {
@@ -283,7 +268,12 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
                     const double amax = fmax(ch->amax, fmax(fabs(ak), ch->beta_prev));
                     ch->amax = amax;
                     ch->steps = step;
-                    if (step >= sw.m_eff || bk <= a.eps * amax) {
+                    // a non-finite coefficient ends the chain and marks it
+                    // (the host reports FTLM_E_NUMERIC); the comparison below
+                    // is false for NaN, so without this the chain would run on
+                    const bool fault = !(isfinite(ak) && isfinite(bk));
+                    if (fault) ch->fault = 1;
+                    if (fault || step >= sw.m_eff || bk <= a.eps * amax) {
                         sw.state[1] -= 1;
                         ch->active = 0;
                         ch->s_cur = 0.0;

@@ -7,15 +7,8 @@ namespace ftlm {
 template <typename T>
 hipError_t launch_hv_typed(const SectorDev&, const BondTable&, const HvLaunch&, hipStream_t);
 
-template <typename T>
-hipError_t launch_split_typed(const SectorDev&, const BondTable&, const HvLaunch&, hipStream_t);
-
 hipError_t launch_hv(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st) {
     return h.dtype == 0 ? launch_hv_typed<float>(s, B, h, st) : launch_hv_typed<double>(s, B, h, st);
-}
-
-hipError_t launch_hv_split(const SectorDev& s, const BondTable& B2, const HvLaunch& h, hipStream_t st) {
-    return h.dtype == 0 ? launch_split_typed<float>(s, B2, h, st) : launch_split_typed<double>(s, B2, h, st);
 }
 
 namespace {

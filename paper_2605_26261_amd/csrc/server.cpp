@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -84,6 +85,9 @@ int request_layout(int n_sites, int n_up, int R, int mode, int dtype, ReqLayout&
 int check_request(const ftlm_request* q) {
     if (!q || !q->bi || !q->bj || !q->J || (q->nT > 0 && !q->T)) return fail(FTLM_E_INVALID, "null argument");
     if (q->n_sites < 2 || q->n_sites > kMaxSites) return fail(FTLM_E_RANGE, "n_sites %d", q->n_sites);
+    if (q->n_bonds < 1 || q->n_bonds > kMaxBonds)
+        return fail(FTLM_E_RANGE, "n_bonds %d not in [1, %d]", q->n_bonds, kMaxBonds);
+    if (!std::isfinite(q->g)) return fail(FTLM_E_INVALID, "g is not finite");
     if (q->n_up < 0 || q->n_up > q->n_sites) return fail(FTLM_E_INVALID, "n_up %d", q->n_up);
     if (q->R < 1 || q->R > kMaxChains) return fail(FTLM_E_RANGE, "R %d not in [1, %d]", q->R, kMaxChains);
     if (q->M < 1 || q->M > kMaxSteps) return fail(FTLM_E_RANGE, "M %d", q->M);
@@ -208,7 +212,7 @@ void ftlm_server::retire(const std::shared_ptr<Request>& r) {
         sr.R = R;
         sr.stride = M;
         sr.dim = r->sector->dim;
-        sr.mult = (2 * r->n_up == r->n_sites) ? 1.0 : 2.0;
+        sr.mult = sector_multiplicity(r->n_sites, r->n_up);
         sr.theta = th.data();
         sr.weight = w.data();
         sr.steps = steps.data();
@@ -255,7 +259,6 @@ int ftlm_server::round() {
             desc_host[slot + g.secs.size()] = w;
             g.secs.push_back(w);
             g.lds = std::max(g.lds, r->job.lds);
-            g.any_split = g.any_split || r->job.any_split;
             ids.push_back(r->id);
         }
         g.grid = int(block);

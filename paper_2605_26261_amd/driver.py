@@ -9,8 +9,8 @@ from . import ftlm
 
 
 def multiplicity(n_sites, n_up):
-    """Sectors +M and -M share a spectrum (Sec. 2): weight 2 for M > 0."""
-    return 1.0 if 2 * n_up == n_sites else 2.0
+    """The sector's weight in the thermal sums (ftlm_sector_info)."""
+    return ftlm.sector_info(n_sites, n_up)[1]
 
 
 def log_temperatures(n=200, t_min=0.05, t_max=10.0):
@@ -57,9 +57,8 @@ def run(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, t
 
 def plan_records(plan, n_sites, seed, dist, r0=0, use_graph=True):
     """One run of an all-sector plan -> per-sector thermo records."""
-    import math
     alpha, beta, steps = plan.run(seed, dist, r0=r0, use_graph=use_graph)
-    return [records_from_coefficients(n_sites, nu, math.comb(n_sites, nu), alpha[i], beta[i], steps[i])
+    return [records_from_coefficients(n_sites, nu, ftlm.sector_info(n_sites, nu)[0], alpha[i], beta[i], steps[i])
             for i, nu in enumerate(plan.n_ups)]
 
 

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libftlm.so")
 
-OK, E_INVALID, E_RANGE, E_NOSPACE, E_DEVICE, E_AGAIN, E_REJECTED = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVALID, E_RANGE, E_NOSPACE, E_DEVICE, E_AGAIN, E_REJECTED, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6, -7
 CLT, CR = 0, 1
 F32, F64 = 0, 1
 PM1, GAUSS, UNIT = 0, 1, 2
@@ -57,8 +57,7 @@ _sig("ftlm_graph_create", _i32, [_i32, _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]
 _sig("ftlm_graph_destroy", None, [_vp])
 _sig("ftlm_graph_n_sites", _i32, [_vp])
 _sig("ftlm_graph_n_bonds", _i32, [_vp])
-_sig("ftlm_graph_split", _i32, [_vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
-_sig("ftlm_set_split_policy", _i32, [_i32])
+_sig("ftlm_sector_info", _i32, [_i32, _i32, ctypes.POINTER(_u64), ctypes.POINTER(_dbl)])
 _sig("ftlm_sector_table_bytes", _i32, [_i32, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("ftlm_sector_create", _i32, [_i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)])
 _sig("ftlm_sector_dim", _u64, [_vp])
@@ -172,14 +171,6 @@ def version():
     return _lib.ftlm_version()
 
 
-SPLIT_OFF, SPLIT_ON = 0, 1
-
-
-def set_split_policy(policy):
-    """ftlm_set_split_policy (process-wide; later launches and runs)."""
-    _check(_lib.ftlm_set_split_policy(policy))
-
-
 class Graph:
     """ftlm_graph: bonds [(i, j, J)] on n_sites sites."""
 
@@ -196,17 +187,17 @@ class Graph:
     def n_bonds(self):
         return _lib.ftlm_graph_n_bonds(self.handle)
 
-    def split(self):
-        """ftlm_graph_split: (site_order int32[N], c, s) of the two-pass H.x."""
-        order = np.zeros(self.n_sites, dtype=np.int32)
-        c, s = _i32(), _i32()
-        _check(_lib.ftlm_graph_split(self.handle, _hptr(order), ctypes.byref(c), ctypes.byref(s)))
-        return order, c.value, s.value
-
     def __del__(self, _destroy=_lib.ftlm_graph_destroy):
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None
+
+
+def sector_info(n_sites, n_up):
+    """ftlm_sector_info: (D, multiplicity) of the sector n_up of n_sites sites."""
+    d, m = _u64(), _dbl()
+    _check(_lib.ftlm_sector_info(n_sites, n_up, ctypes.byref(d), ctypes.byref(m)))
+    return int(d.value), float(m.value)
 
 
 def sector_table_bytes(n_sites, n_up, mode):
@@ -237,11 +228,23 @@ class Sector:
             self.handle = None
 
 
+def _need_u64(*ts):
+    """The C ABI takes uint64 arrays: 8-byte integer tensors of one length."""
+    import torch
+    for t in ts:
+        if t.dtype not in (torch.int64, torch.uint64):
+            raise ValueError("labels and indices must be 8-byte integer tensors")
+    if len({t.numel() for t in ts}) != 1:
+        raise ValueError("labels and indices must have the same number of entries")
+
+
 def rank(sector, labels, idx, stream=None):
+    _need_u64(labels, idx)
     _check(_lib.ftlm_rank(sector.handle, _dptr(labels), _dptr(idx), labels.numel(), _stream(stream)))
 
 
 def unrank(sector, idx, labels, stream=None):
+    _need_u64(idx, labels)
     _check(_lib.ftlm_unrank(sector.handle, _dptr(idx), _dptr(labels), idx.numel(), _stream(stream)))
 
 
@@ -253,6 +256,9 @@ def clt_export(sector, nblocks, stream=None):
 
 
 def neighbors(sector, graph, t0, count, out, stream=None):
+    import torch
+    if out.dtype not in (torch.int64, torch.uint64) or out.numel() < count * graph.n_bonds:
+        raise ValueError("out must be an 8-byte integer tensor of at least count * n_bonds entries")
     _check(_lib.ftlm_neighbors(sector.handle, graph.handle, t0, count, _dptr(out), _stream(stream)))
 
 
@@ -265,14 +271,32 @@ def _dtype_code(t):
     raise ValueError("vectors must be float32 or float64")
 
 
+def _vector_block(x, rows, what="x"):
+    """Number of columns of a [rows] or [rows, B] vector block."""
+    if x.dim() not in (1, 2) or x.shape[0] != rows:
+        raise ValueError(f"{what} must have shape [{rows}] or [{rows}, B], got {tuple(x.shape)}")
+    return 1 if x.dim() == 1 else x.shape[1]
+
+
+def _same_block(x, y):
+    if y.dtype != x.dtype:
+        raise ValueError(f"y has dtype {y.dtype}, x has {x.dtype}")
+
+
 def hv(sector, graph, x, y, stream=None):
     """y = H x for x, y of shape [D] or [D, B]."""
-    nvec = 1 if x.dim() == 1 else x.shape[1]
+    nvec = _vector_block(x, sector.dim)
+    _same_block(x, y)
+    if y.shape != x.shape:
+        raise ValueError(f"y has shape {tuple(y.shape)}, x has {tuple(x.shape)}")
     _check(_lib.ftlm_hv(sector.handle, graph.handle, _dptr(x), _dptr(y), nvec, _dtype_code(x), _stream(stream)))
 
 
 def hv_rows(sector, graph, x, y, row0, nrows, stream=None):
-    nvec = 1 if x.dim() == 1 else x.shape[1]
+    nvec = _vector_block(x, sector.dim)
+    _same_block(x, y)
+    if y.dim() != x.dim() or y.shape[0] < nrows or y.shape[1:] != x.shape[1:]:
+        raise ValueError(f"y must hold at least nrows = {nrows} rows of the columns of x")
     _check(_lib.ftlm_hv_rows(sector.handle, graph.handle, _dptr(x), _dptr(y), nvec, _dtype_code(x),
                              row0, nrows, _stream(stream)))
 
@@ -285,6 +309,10 @@ def lanczos_workspace_bytes(sector, R, dtype):
 
 def start_vectors(sector, seed, r0, R, dist, q, work, stream=None):
     """Writes R start vectors into q [D, R]; returns their FP64 norms."""
+    if _vector_block(q, sector.dim, "q") != R:
+        raise ValueError(f"q must hold R = {R} columns")
+    if work.numel() < lanczos_workspace_bytes(sector, R, _dtype_code(q)):
+        raise ValueError("work is smaller than lanczos_workspace_bytes(sector, R, dtype)")
     norms = np.empty(R, dtype=np.float64)
     _check(_lib.ftlm_start_vectors(sector.handle, seed, r0, R, dist, _dtype_code(q), _dptr(q), _hptr(norms),
                                    _dptr(work), work.numel(), _stream(stream)))

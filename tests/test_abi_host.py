@@ -72,49 +72,33 @@ def test_graph_validation(ftlm):
         ftlm.Graph(30, [(i, j, 1.0) for i in range(30) for j in range(i + 1, 30)][:129])
 
 
-def _check_split(n, bonds, order, c, s):
-    assert sorted(order) == list(range(n))
-    assert 0 <= c < s < n
-    for i, j, _ in bonds:
-        lo, hi = sorted((int(order[i]), int(order[j])))
-        # inside [0, s), or joining [s, N) to [0, c) or to itself
-        assert hi < s or lo < c or lo >= s
+def test_sector_info(ftlm):
+    # D = C(N, n_up) and the weight of the sector in the thermal sums (1 for
+    # M = 0, 2 for a sector standing for +M and -M)
+    assert ftlm.sector_info(30, 15) == (155117520, 1.0)
+    assert ftlm.sector_info(34, 17) == (2333606220, 1.0)
+    assert ftlm.sector_info(24, 13) == (math.comb(24, 13), 2.0)
+    assert ftlm.sector_info(7, 4) == (35, 2.0)
+    assert ftlm.sector_info(64, 32)[0] == math.comb(64, 32)
+    for bad, code in (((65, 2), ftlm.E_RANGE), ((10, 11), ftlm.E_INVALID), ((10, -1), ftlm.E_INVALID)):
+        with pytest.raises(ftlm.FtlmError) as e:
+            ftlm.sector_info(*bad)
+        assert e.value.code == code
 
 
-@pytest.mark.parametrize("name,n,bonds,block", [
-    # largest block of either pass, in rows: C(s, s/2) and C(N - s + c, .)
-    ("icosidodecahedron", 30, graphs.icosidodecahedron(), math.comb(18, 9)),
-    ("j1j2_ring34", 34, graphs.j1j2_ring(34, 1.0, 0.3), math.comb(19, 9)),
-    ("square6x4", 24, graphs.square_j1j2(6, 4, 1.0, 0.5), math.comb(16, 8)),
-    ("dodecahedron", 20, graphs.dodecahedron(), math.comb(13, 6)),
-])
-def test_graph_split(ftlm, name, n, bonds, block):
-    g = ftlm.Graph(n, bonds)
-    order, c, s = g.split()
-    _check_split(n, bonds, order, c, s)
-    assert max(math.comb(s, s // 2), math.comb(n - s + c, (n - s + c) // 2)) <= block
-    # relabelled by its own order, a graph keeps its labels
-    rb = [(int(order[i]), int(order[j]), J) for i, j, J in bonds]
-    o2, c2, s2 = ftlm.Graph(n, rb).split()
-    assert list(o2) == list(range(n)) and (c2, s2) == (c, s)
-
-
-def test_graph_split_random_and_small(ftlm):
-    rng = np.random.default_rng(11)
-    for n in (16, 20, 24, 28):
-        bonds = graphs.random_cluster(n, rng)
-        order, c, s = ftlm.Graph(n, bonds).split()
-        if s:
-            _check_split(n, bonds, order, c, s)
-    # a graph without a useful split reports none and the identity order
-    order, c, s = ftlm.Graph(6, graphs.ring(6)).split()
-    assert (c, s) == (0, 0) and list(order) == list(range(6))
-    full = [(i, j, 1.0) for i in range(12) for j in range(i + 1, 12)]
-    order, c, s = ftlm.Graph(12, full).split()
-    assert (c, s) == (0, 0)
-    with pytest.raises(ftlm.FtlmError):
-        ftlm.set_split_policy(7)
-    ftlm.set_split_policy(ftlm.SPLIT_OFF)
+def test_server_request_validation(ftlm):
+    # request checks run on the host (no device call)
+    bonds = graphs.ring(8)
+    assert ftlm.server_request_bytes(8, bonds, 4, 4, 10, ftlm.CR, ftlm.F32) > 0
+    q, keep = ftlm._request(8, bonds, 4, 4, 10, 0, ftlm.PM1, (1.0,), 1.0)
+    n = ctypes.c_size_t()
+    for field, value, code in (("n_bonds", -3, ftlm.E_RANGE), ("n_bonds", 0, ftlm.E_RANGE),
+                               ("n_bonds", 129, ftlm.E_RANGE), ("g", float("nan"), ftlm.E_INVALID),
+                               ("g", float("inf"), ftlm.E_INVALID), ("R", 0, ftlm.E_RANGE)):
+        bad = ftlm.Request.from_buffer_copy(q)
+        setattr(bad, field, value)
+        rc = ftlm._lib.ftlm_server_request_bytes(ctypes.byref(bad), ftlm.CR, ftlm.F32, ctypes.byref(n))
+        assert rc == code, (field, value, rc)
 
 
 @pytest.mark.parametrize("m", [1, 2, 3, 7, 40, 100, 300])

@@ -251,3 +251,61 @@ def test_staged_and_strided_updates_agree(env, dt, R, chunks):
         np.testing.assert_array_equal(b[r0:r0 + w], b1)
         np.testing.assert_array_equal(s[r0:r0 + w], s1)
     assert np.all(s == M) and np.all(b[:, : M - 1] > 0)
+
+
+def test_binding_checks_buffer_shapes(env):
+    # the binding refuses buffers the kernels would read or write past
+    torch, ftlm = env
+    n, n_up = 12, 6
+    g = ftlm.Graph(n, graphs.ring(n))
+    sec = ftlm.Sector(n, n_up, ftlm.CR)
+    d = sec.dim
+    x = torch.randn(d, 3, device="cuda")
+    for y in (torch.empty(d, 2, device="cuda"), torch.empty(d - 1, 3, device="cuda"),
+              torch.empty(d, 3, dtype=torch.float64, device="cuda")):
+        with pytest.raises(ValueError):
+            ftlm.hv(sec, g, x, y)
+    with pytest.raises(ValueError):
+        ftlm.hv(sec, g, torch.randn(d + 1, device="cuda"), torch.empty(d + 1, device="cuda"))
+    with pytest.raises(ValueError):
+        ftlm.hv_rows(sec, g, x, torch.empty(10, 3, device="cuda"), 0, 11)
+    with pytest.raises(ValueError):
+        ftlm.hv(sec, g, x.half(), x.half())
+    labels = torch.zeros(5, dtype=torch.int64, device="cuda")
+    for idx in (torch.zeros(5, dtype=torch.int32, device="cuda"), torch.zeros(4, dtype=torch.int64, device="cuda")):
+        with pytest.raises(ValueError):
+            ftlm.rank(sec, labels, idx)
+        with pytest.raises(ValueError):
+            ftlm.unrank(sec, idx, labels)
+    with pytest.raises(ValueError):
+        ftlm.neighbors(sec, g, 0, 4, torch.empty(4 * g.n_bonds - 1, dtype=torch.int64, device="cuda"))
+    work = torch.empty(ftlm.lanczos_workspace_bytes(sec, 3, ftlm.F32), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        ftlm.start_vectors(sec, 1, 0, 4, ftlm.PM1, x, work)
+    with pytest.raises(ValueError):
+        ftlm.start_vectors(sec, 1, 0, 3, ftlm.PM1, x, work[:-1])
+
+
+def test_non_finite_coefficients_stop_the_chain(env):
+    # couplings so large that the FP32 products overflow: every chain's
+    # alpha_1 or beta_1 comes out infinite or NaN, the chain stops at step 1
+    # and the call reports FTLM_E_NUMERIC (every kernel still runs to its end)
+    torch, ftlm = env
+    n, n_up = 12, 6
+    g = ftlm.Graph(n, [(i, (i + 1) % n, 3e38) for i in range(n)])
+    sec = ftlm.Sector(n, n_up, ftlm.CR)
+    R, M = 4, 20
+    work = torch.empty(ftlm.lanczos_workspace_bytes(sec, R, ftlm.F32), dtype=torch.uint8, device="cuda")
+    alpha = np.zeros((R, M))
+    beta = np.zeros((R, M))
+    steps = np.zeros(R, dtype=np.int32)
+    rc = ftlm._lib.ftlm_lanczos(sec.handle, g.handle, 1, 0, R, M, ftlm.PM1, ftlm.F32, ftlm._dptr(work),
+                                work.numel(), ftlm._hptr(alpha), ftlm._hptr(beta), ftlm._hptr(steps),
+                                ftlm._stream(None))
+    assert rc == ftlm.E_NUMERIC
+    assert np.all(steps == 1)
+    assert not np.all(np.isfinite(alpha[:, 0]) & np.isfinite(beta[:, 0]))
+    # a sane graph on the same sector and workspace still runs every step
+    g1 = ftlm.Graph(n, graphs.ring(n))
+    a, b, s = ftlm.lanczos(sec, g1, 1, 0, R, M, ftlm.PM1, ftlm.F32, work)
+    assert np.all(s == M) and np.all(np.isfinite(a)) and np.all(np.isfinite(b))
