@@ -56,7 +56,7 @@ def _sampled_rows(y, d, rng, n_windows, per_window):
     rows, vals = [], []
     for a in _windows(d, rng, n_windows):
         w = y.narrow(0, a, WINDOW).cpu().double().numpy()
-        pick = np.unique(rng.integers(0, WINDOW, per_window))
+        pick = np.sort(rng.choice(WINDOW, per_window, replace=False))
         rows.append(a + pick)
         vals.append(w[pick])
     return np.concatenate(rows).astype(np.uint64), np.concatenate(vals)
