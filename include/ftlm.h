@@ -210,6 +210,24 @@ int ftlm_lanczos(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint6
                  int M, int dist, int dtype, void* work_dev, size_t work_bytes, double* alpha_host,
                  double* beta_host, int32_t* steps_host, void* stream);
 
+/* ftlm_lanczos_noalloc: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). It runs ftlm_lanczos, same kernels and same results bit for
+ * bit, with the workspace taken from a device array of
+ * FTLM_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends; it allocates no device memory. Arguments are those
+ * of ftlm_lanczos without work_dev/work_bytes. The sector's tables must sit
+ * on the current device (FTLM_E_INVALID otherwise). A call whose workspace
+ * (ftlm_lanczos_workspace_bytes(s, R, dtype)) exceeds the array returns
+ * FTLM_E_RANGE before any device work. Every call on a GPU shares that GPU's
+ * array, which keeps the last call's contents (each call clears the counters
+ * and chain state it needs): calls that overlap on one GPU, from two streams
+ * or two threads, race and must not be made. */
+#define FTLM_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int ftlm_lanczos_noalloc(const ftlm_sector* s, const ftlm_graph* g, uint64_t seed, uint64_t r0,
+                         int R, int M, int dist, int dtype, double* alpha_host, double* beta_host,
+                         int32_t* steps_host, void* stream);
+
 /* ---- autotuning of the batch width -------------------------------------------
  * The B chains of a Lanczos batch share each row's index work (Sec. 2,
  * batched Lanczos; the paper picks B adaptively, Sec. 3.4). ftlm_autotune

@@ -72,6 +72,7 @@ _sig("ftlm_hv_rows", _i32, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _u64, _vp])
 _sig("ftlm_start_vectors", _i32, [_vp, _u64, _u64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp])
 _sig("ftlm_lanczos_workspace_bytes", _i32, [_vp, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("ftlm_lanczos", _i32, [_vp, _vp, _u64, _u64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _vp])
+_sig("ftlm_lanczos_noalloc", _i32, [_vp, _vp, _u64, _u64, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp])
 _sig("ftlm_plan_workspace_bytes", _i32, [_vp, _i32, _vp, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("ftlm_plan_create", _i32, [_vp, _i32, _vp, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)])
 _sig("ftlm_plan_run", _i32, [_vp, _u64, _u64, _i32, _i32, _vp, _vp, _vp, _vp])
@@ -328,6 +329,20 @@ def lanczos(sector, graph, seed, r0, R, M, dist, dtype, work=None, stream=None):
     steps = np.zeros(R, dtype=np.int32)
     _check(_lib.ftlm_lanczos(sector.handle, graph.handle, seed, r0, R, M, dist, dtype, _dptr(work), work.numel(),
                              _hptr(alpha), _hptr(beta), _hptr(steps), _stream(stream)))
+    return alpha, beta, steps
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20  # FTLM_NOALLOC_SCRATCH_BYTES
+
+
+def lanczos_noalloc(sector, graph, seed, r0, R, M, dist, dtype, stream=None):
+    """ftlm_lanczos_noalloc: lanczos() with the workspace in the library's
+    per-device array (no device allocation); returns (alpha, beta, steps)."""
+    alpha = np.zeros((R, M), dtype=np.float64)
+    beta = np.zeros((R, M), dtype=np.float64)
+    steps = np.zeros(R, dtype=np.int32)
+    _check(_lib.ftlm_lanczos_noalloc(sector.handle, graph.handle, seed, r0, R, M, dist, dtype, _hptr(alpha),
+                                     _hptr(beta), _hptr(steps), _stream(stream)))
     return alpha, beta, steps
 
 
