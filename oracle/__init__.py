@@ -317,6 +317,56 @@ def ritz(alpha, beta, steps=None):
     return theta, s[0, :] ** 2
 
 
+U_FP32 = 2.0 ** -24  # unit roundoff of IEEE single precision
+
+
+def seed_spread(estimates):
+    """Empirical standard deviation of Eq. (22) over N_s independent FTLM
+    runs: ``estimates`` is [N_s][...] (one row per seed); returns (mean,
+    sigma) with sigma^2 = (1/N_s) sum_s (O_s - mean)^2."""
+    x = np.asarray(estimates, dtype=np.float64)
+    n_s = x.shape[0]
+    mean = x.sum(axis=0) / n_s
+    dev = x - mean[None, ...]
+    return mean, np.sqrt((dev * dev).sum(axis=0) / n_s)
+
+
+def ghost_diagnostic(alpha, beta, steps=None, c_tau=1.0, u=U_FP32):
+    """Cullum-Willoughby ghost test and Ritz clusters (Sec. 3.2, Eq. 25).
+
+    T is the steps x steps tridiagonal of one chain; T1 is T without its first
+    row and column. A Ritz value theta_k of T is a ghost when its deflation
+    distance ell_k = min_j |theta_k - theta1_j| (theta1 the eigenvalues of T1)
+    is below tau = c_tau * u * (max theta - min theta). Ritz values whose
+    distance is <= tau belong to one cluster (joined transitively along the
+    sorted spectrum). Returns a dict: theta (ascending), weight, ell, tau,
+    ghost (bool), cluster (cluster id per theta_k, ids in ascending order) and
+    cluster_weight (total weight per cluster id)."""
+    from scipy.linalg import eigvalsh_tridiagonal
+    if steps is None:
+        steps = len(alpha)
+    theta, w = ritz(alpha, beta, steps)
+    if steps >= 2:
+        a1 = np.asarray(alpha[1:steps], dtype=np.float64)
+        if steps >= 3:
+            theta1 = eigvalsh_tridiagonal(a1, np.asarray(beta[1:steps - 1], dtype=np.float64),
+                                          lapack_driver="stev")
+        else:
+            theta1 = a1.copy()
+        ell = np.array([float(np.min(np.abs(t - theta1))) for t in theta])
+    else:
+        ell = np.full(1, np.inf)
+    tau = c_tau * u * float(theta[-1] - theta[0])
+    cluster = np.zeros(steps, dtype=np.int64)
+    for k in range(1, steps):
+        cluster[k] = cluster[k - 1] + (0 if theta[k] - theta[k - 1] <= tau else 1)
+    cw = np.zeros(int(cluster[-1]) + 1)
+    for k in range(steps):
+        cw[cluster[k]] += w[k]
+    return {"theta": theta, "weight": w, "ell": ell, "tau": tau, "ghost": ell < tau, "cluster": cluster,
+            "cluster_weight": cw}
+
+
 def log_temperatures(n=200, t_min=0.05, t_max=10.0):
     """n log-spaced temperatures from t_min to t_max inclusive."""
     k = np.arange(n)
