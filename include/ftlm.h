@@ -430,6 +430,30 @@ typedef struct ftlm_sector_result {
 int ftlm_thermo(int n_sites, int n_sectors, const ftlm_sector_result* sectors, int nT,
                 const double* T, double g, double* E, double* C, double* chi, double* lnZ);
 
+/* ---- precision diagnostics (Sec. 3.1-3.2) ------------------------------------
+ * ftlm_ghosts: the Cullum-Willoughby ghost test of Eq. (25) on one chain's
+ * m x m tridiagonal T (alpha[m], beta[m-1], host arrays). theta, weight:
+ * the Ritz values of T in ascending order and their weights (as
+ * ftlm_ritz). ell[k] = min_j |theta_k - theta1_j| over the eigenvalues
+ * theta1 of T1, the matrix T without its first row and column (ell = +inf
+ * when m = 1). ghost[k] = 1 when ell[k] < tau, with the tolerance the paper
+ * applies to both precisions, tau = c_tau * u_FP32 * (theta_max - theta_min),
+ * u_FP32 = 2^-24 (c_tau: a factor of order one). cluster[k]: the cluster of
+ * theta_k, numbered in ascending order; neighbouring Ritz values within tau
+ * of each other share a cluster (Fig. 5's clusters). cluster_weight[c]:
+ * the total weight of cluster c for c < *n_clusters (0 beyond). All outputs
+ * hold m entries. FTLM_E_INVALID for a bad argument or a QL iteration that
+ * does not converge. */
+int ftlm_ghosts(int m, const double* alpha, const double* beta, double c_tau, double* theta,
+                double* weight, double* ell, int32_t* ghost, int32_t* cluster,
+                double* cluster_weight, int32_t* n_clusters, double* tau);
+
+/* ftlm_seed_spread: Eq. (22) over N_s independent FTLM estimates. values is
+ * a [n_seeds][n] host array (row s: one run's observable at n points, for
+ * example n temperatures); mean[n] and sigma[n] receive the mean over seeds
+ * and sigma_emp = sqrt((1/N_s) sum_s (O_s - mean)^2). */
+int ftlm_seed_spread(int n_seeds, int n, const double* values, double* mean, double* sigma);
+
 /* ---- measurement hooks ---------------------------------------------------
  * When enabled, the library records a pair of HIP events around every H.x
  * launch on the launch's own stream and accumulates their elapsed times;

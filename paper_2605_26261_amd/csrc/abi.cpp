@@ -675,6 +675,26 @@ int ftlm_ritz_batch(int n, int stride, const int32_t* m, const double* alpha, co
     return ok();
 }
 
+int ftlm_ghosts(int m, const double* alpha, const double* beta, double c_tau, double* theta, double* weight,
+                double* ell, int32_t* ghost, int32_t* cluster, double* cluster_weight, int32_t* n_clusters,
+                double* tau) {
+    if (m < 1 || !alpha || (m > 1 && !beta) || !theta || !weight || !ell || !ghost || !cluster || !cluster_weight ||
+        !n_clusters || !tau)
+        return fail(FTLM_E_INVALID, "bad argument");
+    if (!(c_tau >= 0.0) || !std::isfinite(c_tau)) return fail(FTLM_E_INVALID, "c_tau %g is not a finite value >= 0", c_tau);
+    if (ghost_test(m, alpha, beta, c_tau, kUnitRoundoffF32, theta, weight, ell, ghost, cluster, cluster_weight,
+                   n_clusters, tau) != 0)
+        return fail(FTLM_E_INVALID, "QL iteration did not converge");
+    return ok();
+}
+
+int ftlm_seed_spread(int n_seeds, int n, const double* values, double* mean, double* sigma) {
+    if (n_seeds < 1 || n < 0 || (n && (!values || !mean || !sigma)))
+        return fail(FTLM_E_INVALID, "n_seeds = %d, n = %d", n_seeds, n);
+    seed_spread(n_seeds, n, values, mean, sigma);
+    return ok();
+}
+
 int ftlm_thermo(int n_sites, int n_sectors, const ftlm_sector_result* sectors, int nT, const double* T, double g,
                 double* E, double* C, double* chi, double* lnZ) {
     if (n_sectors < 1 || !sectors || nT < 0 || (nT && !T)) return fail(FTLM_E_INVALID, "bad argument");

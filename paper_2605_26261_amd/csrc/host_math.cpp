@@ -139,6 +139,59 @@ int ritz_batch(int n, int stride, const int32_t* m, const double* alpha, const d
     return failed.load() ? -1 : 0;
 }
 
+// Cullum-Willoughby ghost test (Sec. 3.2, Eq. 25) of one chain: the Ritz
+// values of T, the eigenvalues of T1 (T without its first row and column),
+// the deflation distance of every Ritz value to the nearest eigenvalue of
+// T1, the flag ell_k < tau with tau = c_tau * u * (theta_max - theta_min),
+// and clusters of Ritz values joined along the sorted spectrum wherever two
+// neighbours lie within tau, with their total weights.
+int ghost_test(int m, const double* alpha, const double* beta, double c_tau, double u, double* theta,
+               double* weight, double* ell, int32_t* ghost, int32_t* cluster, double* cluster_weight,
+               int32_t* n_clusters, double* tau) {
+    if (ritz_ql(m, alpha, beta, theta, weight) != 0) return -1;
+    std::vector<double> t1(size_t(m > 1 ? m - 1 : 1)), w1(t1.size());
+    if (m > 1 && ritz_ql(m - 1, alpha + 1, beta + 1, t1.data(), w1.data()) != 0) return -1;
+    const double tol = c_tau * u * (theta[m - 1] - theta[0]);
+    for (int k = 0; k < m; ++k) {
+        double best = INFINITY;
+        if (m > 1) {
+            // t1 is ascending: the nearest value is at or just below the insertion point
+            const auto it = std::lower_bound(t1.begin(), t1.begin() + (m - 1), theta[k]);
+            if (it != t1.begin() + (m - 1)) best = std::fabs(*it - theta[k]);
+            if (it != t1.begin()) best = std::min(best, std::fabs(*(it - 1) - theta[k]));
+        }
+        ell[k] = best;
+        ghost[k] = best < tol ? 1 : 0;
+    }
+    int c = 0;
+    for (int k = 0; k < m; ++k) {
+        if (k > 0 && theta[k] - theta[k - 1] > tol) ++c;
+        cluster[k] = c;
+    }
+    for (int k = 0; k < m; ++k) cluster_weight[k] = 0.0;
+    for (int k = 0; k < m; ++k) cluster_weight[cluster[k]] += weight[k];
+    *n_clusters = c + 1;
+    *tau = tol;
+    return 0;
+}
+
+// Spread over seeds of Eq. (22): per column j of [n_seeds][n] values, the mean
+// and sigma = sqrt((1/N_s) sum_s (v_sj - mean_j)^2), summed in seed order.
+void seed_spread(int n_seeds, int n, const double* v, double* mean, double* sigma) {
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int r = 0; r < n_seeds; ++r) s += v[size_t(r) * size_t(n) + size_t(j)];
+        const double mu = s / double(n_seeds);
+        double q = 0.0;
+        for (int r = 0; r < n_seeds; ++r) {
+            const double d = v[size_t(r) * size_t(n) + size_t(j)] - mu;
+            q += d * d;
+        }
+        mean[j] = mu;
+        sigma[j] = std::sqrt(q / double(n_seeds));
+    }
+}
+
 // FTLM thermal reduction (Eqs. 6-9). Per sector the estimator weighs each
 // sample's Gauss-quadrature sum by mult * D / R; Boltzmann factors use
 // theta - E0 with E0 the smallest Ritz value of all samples, which cancels in

@@ -80,6 +80,8 @@ _sig("ftlm_plan_tune", _i32, [_vp, _vp, _vp])
 _sig("ftlm_plan_destroy", None, [_vp])
 _sig("ftlm_ritz", _i32, [_i32, _vp, _vp, _vp, _vp])
 _sig("ftlm_ritz_batch", _i32, [_i32, _i32, _vp, _vp, _vp, _vp, _vp])
+_sig("ftlm_ghosts", _i32, [_i32, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_dbl)])
+_sig("ftlm_seed_spread", _i32, [_i32, _i32, _vp, _vp, _vp])
 _sig("ftlm_thermo", _i32, [_i32, _i32, ctypes.POINTER(SectorResult), _i32, _vp, _dbl, _vp, _vp, _vp, _vp])
 _sig("ftlm_stats_enable", _i32, [_i32])
 _sig("ftlm_stats_reset", _i32, [])
@@ -481,6 +483,37 @@ def ritz(alpha, beta, m=None):
     weight = np.empty(m, dtype=np.float64)
     _check(_lib.ftlm_ritz(m, _hptr(alpha), _hptr(beta), _hptr(theta), _hptr(weight)))
     return theta, weight
+
+
+def ghosts(alpha, beta, m=None, c_tau=1.0):
+    """ftlm_ghosts: Cullum-Willoughby ghost test (Eq. 25) and Ritz clusters of
+    one chain; returns a dict of theta, weight, ell, ghost (bool), cluster,
+    cluster_weight (per cluster) and tau."""
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    m = len(alpha) if m is None else m
+    if m < 1 or m > len(alpha) or (m > 1 and len(beta) < m - 1):
+        raise ValueError("alpha needs m entries and beta m - 1")
+    theta, weight, ell, cw = (np.empty(m, dtype=np.float64) for _ in range(4))
+    ghost, cluster = np.empty(m, dtype=np.int32), np.empty(m, dtype=np.int32)
+    nc, tau = _i32(), _dbl()
+    _check(_lib.ftlm_ghosts(m, _hptr(alpha), _hptr(beta), c_tau, _hptr(theta), _hptr(weight), _hptr(ell),
+                            _hptr(ghost), _hptr(cluster), _hptr(cw), ctypes.byref(nc), ctypes.byref(tau)))
+    return {"theta": theta, "weight": weight, "ell": ell, "ghost": ghost.astype(bool), "cluster": cluster,
+            "cluster_weight": cw[:nc.value].copy(), "tau": tau.value}
+
+
+def seed_spread(estimates):
+    """ftlm_seed_spread: (mean, sigma_emp) over the rows of [N_s][n] (Eq. 22)."""
+    v = np.ascontiguousarray(estimates, dtype=np.float64)
+    if v.ndim < 1 or v.shape[0] < 1:
+        raise ValueError("estimates need at least one seed (one row)")
+    shape = v.shape[1:]
+    v = v.reshape(v.shape[0], -1)
+    mean = np.empty(v.shape[1], dtype=np.float64)
+    sigma = np.empty(v.shape[1], dtype=np.float64)
+    _check(_lib.ftlm_seed_spread(v.shape[0], v.shape[1], _hptr(v), _hptr(mean), _hptr(sigma)))
+    return mean.reshape(shape), sigma.reshape(shape)
 
 
 def ritz_batch(alpha, beta, steps):

@@ -230,3 +230,59 @@ def test_server_options_validated_before_any_device_work(ftlm):
         rc = ftlm._lib.ftlm_server_create(fake_arena, 1 << 30, ctypes.byref(opts), ctypes.byref(h))
         assert rc == code, (kw, rc)
         assert not h.value
+
+
+def _long_chain(n, n_up, bonds, steps, seed):
+    """FP64 Lanczos far past convergence (no stopping, no reorthogonalization)."""
+    b = oracle.basis(n, n_up)
+    q = oracle.start_vector(seed, n_up, 0, oracle.GAUSS, len(b))
+    qp, bp, al, be = np.zeros_like(q), 0.0, [], []
+    for _ in range(steps):
+        w = oracle.hv(n, n_up, bonds, q, b) - bp * qp
+        a = float(q @ w)
+        w -= a * q
+        nb = math.sqrt(float(w @ w))
+        al.append(a)
+        be.append(nb)
+        qp, q, bp = q, w / nb, nb
+    return np.array(al), np.array(be)
+
+
+@pytest.mark.parametrize("c_tau", [1.0, 2.0])
+def test_ghosts_match_oracle(ftlm, c_tau):
+    # a chain with ghosts (80 steps in a 70-dimensional sector) and one without
+    a, b = _long_chain(8, 4, graphs.ring(8), 80, 3)
+    rng = np.random.default_rng(1)
+    a2, b2 = 0.1 * rng.normal(size=15), 1.0 + 0.1 * rng.uniform(size=14)
+    for al, be in ((a, b), (a2, b2), (a[:1], b[:0])):
+        got = ftlm.ghosts(al, be, c_tau=c_tau)
+        want = oracle.ghost_diagnostic(al, be, c_tau=c_tau)
+        scale = max(1.0, np.abs(want["theta"]).max())
+        np.testing.assert_allclose(got["theta"], want["theta"], rtol=0, atol=1e-12 * scale)
+        assert got["tau"] == pytest.approx(want["tau"], rel=1e-12)
+        if len(al) == 1:
+            assert np.isinf(got["ell"][0]) and not got["ghost"][0]
+            continue
+        # flags and clusters agree wherever the decision is not within rounding of tau
+        safe = np.abs(want["ell"] - want["tau"]) > 1e-9 * scale
+        np.testing.assert_array_equal(got["ghost"][safe], want["ghost"][safe])
+        np.testing.assert_allclose(got["ell"], want["ell"], rtol=1e-6, atol=1e-12 * scale)
+        gaps = np.diff(want["theta"])
+        if np.all(np.abs(gaps - want["tau"]) > 1e-9 * scale):
+            np.testing.assert_array_equal(got["cluster"], want["cluster"])
+            np.testing.assert_allclose(got["cluster_weight"], want["cluster_weight"], atol=1e-10)
+    g = ftlm.ghosts(a, b, c_tau=c_tau)
+    assert g["ghost"].sum() > 0 and abs(g["cluster_weight"].sum() - 1) < 1e-12
+
+
+def test_seed_spread_matches_oracle(ftlm):
+    rng = np.random.default_rng(2)
+    v = rng.normal(size=(17, 3, 5))
+    m, s = ftlm.seed_spread(v)
+    mo, so = oracle.seed_spread(v)
+    np.testing.assert_allclose(m, mo, rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(s, so, rtol=1e-13)
+    with pytest.raises(ValueError):
+        ftlm.seed_spread(np.zeros((0, 4)))
+    import ctypes as ct
+    assert ftlm._lib.ftlm_seed_spread(0, 4, None, None, None) == ftlm.E_INVALID
