@@ -6,17 +6,17 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "ftlm_oracle.c")
+SRCS = [os.path.join(HERE, "ftlm_oracle.c"), os.path.join(HERE, "spin_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(force=True):
     """Compile liboracle.so next to its source; returns the library path."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+    if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(f) for f in SRCS):
         return LIB
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           SRC, "-o", tmp, "-lm"]
+           *SRCS, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
