@@ -298,6 +298,69 @@ def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True, steps_per
     return out
 
 
+def _precision_summary(ftlm, got, ref, runs, temps, keys):
+    """FP32-vs-FP64 differences of one run against a stored FP64 oracle
+    reference and the spread over seeds (Eq. 22) at the same R."""
+    import numpy as np
+    out = {}
+    for k in keys:
+        o64 = np.asarray(ref[k])
+        d = np.abs(np.asarray(got[k]) - o64)
+        _, sig = ftlm.seed_spread(np.array([r[k] for r in runs]))
+        where = sig >= 1e-3 * sig.max()
+        out[k] = {"max_abs_diff": float(d.max()), "max_rel_to_max": float(d.max() / np.abs(o64).max()),
+                  "max_sigma_emp": float(sig.max()),
+                  "max_diff_over_sigma": float(np.max(d[where] / sig[where]))}
+    return out
+
+
+def precision(n_seeds=10):
+    """The precision pattern: FTLM with FP32 vectors and FP64 reductions
+    against the FP64 oracle's stored results for the same start vectors
+    (tests/golden, written by scripts that call only the oracle), and the
+    stochastic error sigma_emp over n_seeds further seeds at the same R."""
+    import numpy as np
+
+    from ftlm_inputs import graphs
+    from paper_2605_26261_amd import driver, ftlm
+
+    gold = os.path.join(ROOT, "tests", "golden")
+    out = {"n_seeds": n_seeds, "seeds": f"{1000}..{1000 + n_seeds - 1}"}
+    # N = 12 ring, S^z = 0, R = 8 +-1, M = 40 (the FP64 workload): FP32 and FP64 on the GPU
+    ref = json.load(open(os.path.join(gold, "ring12_r8.json")))
+    temps = np.asarray(ref["temps"])
+    rec = {}
+    for name, dt in (("f32", ftlm.F32), ("f64", ftlm.F64)):
+        th, _ = driver.run(12, graphs.ring(12), [6], 8, 40, ref["seed"], ftlm.PM1, dtype=dt, temps=temps)
+        runs = [driver.run(12, graphs.ring(12), [6], 8, 40, 1000 + s, ftlm.PM1, dtype=dt, temps=temps)[0]
+                for s in range(n_seeds)]
+        rec[name] = _precision_summary(ftlm, th, ref, runs, temps, ("E", "C"))
+    out["ring12_R8_M40"] = rec
+    # icosidodecahedron N = 30, S^z = 0, the first 2 Gaussian chains of seed 2, M = 100, both index maps
+    ref = json.load(open(os.path.join(gold, "icosidodecahedron_r2.json")))
+    temps = np.asarray(ref["temps"])
+    bonds = [tuple(b) for b in ref["bonds"]]
+    rec = {}
+    for name, mode in (("clt", ftlm.CLT), ("cr", ftlm.CR)):
+        th, _ = driver.run(30, bonds, [15], 2, 100, ref["seed"], ftlm.GAUSS, mode=mode, temps=temps)
+        if name == "cr":
+            runs = [driver.run(30, bonds, [15], 2, 100, 1000 + s, ftlm.GAUSS, mode=mode, temps=temps)[0]
+                    for s in range(n_seeds)]
+        rec[name] = th
+    out["icosidodecahedron_R2_M100"] = {k: _precision_summary(ftlm, rec[k], ref, runs, temps, ("E", "C"))
+                                        for k in rec}
+    # 6x4 J1-J2 lattice, all 13 sectors, R = 2 +-1, M = 80, one plan
+    ref = json.load(open(os.path.join(gold, "square4x6_r2.json")))
+    temps = np.asarray(ref["temps"])
+    g = ftlm.Graph(24, [tuple(b) for b in ref["bonds"]])
+    plan = ftlm.Plan(g, [sct["n_up"] for sct in ref["sectors"]], ftlm.CR, 2, ref["M"], ftlm.F32)
+    th = ftlm.thermo(24, driver.plan_records(plan, 24, ref["seed"], ftlm.PM1), temps, 1.0)
+    runs = [ftlm.thermo(24, driver.plan_records(plan, 24, 1000 + s, ftlm.PM1), temps, 1.0) for s in range(n_seeds)]
+    out["square4x6_R2_M80"] = _precision_summary(ftlm, th, ref, runs, temps, ("E", "C", "chi"))
+    del plan
+    return out
+
+
 def largest_sector():
     """J1-J2 ring N = 34 (J2 = 0.3), S^z = 0, D = 2,333,606,220, CR only: H.x
     at B = 1 and B = 4, and the whole FTLM run of the workload (R = 4
@@ -338,28 +401,97 @@ def largest_sector():
     return out
 
 
-def cpu_baseline(target_s=15.0):
-    """The FP64 oracle's H.x on a bounded row sample of the same sector."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(target_s=10.0):
+    """The FP64 oracle (plain definitions, never tuned) on the host cores, at
+    all cores and at one thread, each case on a bounded sample:
+
+    * the N = 30 S^z = 0 H.x on a row range (states.bonds/s; the headline
+      figure, also the value of the line);
+    * the N = 12 ring FTLM (R = 8 +-1 chains, M = 40, FP64) whole, repeated
+      to fill the time (samples/s);
+    * the 6x4 J1-J2 lattice: Lanczos steps of one chain in the largest sector
+      (D = 2,704,156), from which the whole all-sector run (416 chains of 80
+      steps) is priced in proportion to D x bonds (samples/s, extrapolated);
+    * the N = 30 R = 2 reference run (200 FP64 H.x), priced from the H.x rate."""
     import numpy as np
 
     import oracle
     from ftlm_inputs import graphs
 
+    ncores = len(os.sched_getaffinity(0))
+    out = {"cpu_model": _cpu_model(), "cores_available": ncores, "cases": {}}
     bonds = graphs.icosidodecahedron()
     dim = math.comb(N_SITES, N_UP)
     x = np.random.default_rng(0).standard_normal(dim)
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    probe = 1 << 16
-    t0 = time.perf_counter()
-    oracle.hv(N_SITES, N_UP, bonds, x, None, row0=0, nrows=probe)
-    tp = time.perf_counter() - t0
-    nrows = int(min(dim, max(probe, probe * target_s / max(tp, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.hv(N_SITES, N_UP, bonds, x, None, row0=0, nrows=nrows)
-    dt = time.perf_counter() - t0
-    return {"value": nrows * len(bonds) / dt, "unit": "states·bonds/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle H.x on rows [0, {nrows}) of the N=30 S^z=0 icosidodecahedron sector "
-                      f"(count-based ranks, no stored basis), {dt:.1f} s"}
+    for threads in (ncores, 1):
+        used = oracle.set_threads(threads)
+        tag = f"{used}t"
+        # N = 30 H.x on rows [0, n)
+        probe = 1 << 14
+        t0 = time.perf_counter()
+        oracle.hv(N_SITES, N_UP, bonds, x, None, row0=0, nrows=probe)
+        tp = time.perf_counter() - t0
+        nrows = int(min(dim, max(probe, probe * target_s / max(tp, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.hv(N_SITES, N_UP, bonds, x, None, row0=0, nrows=nrows)
+        dt = time.perf_counter() - t0
+        rate = nrows * len(bonds) / dt
+        out["cases"][f"hv_n30_{tag}"] = {"value": rate, "unit": "states·bonds/s", "threads": used,
+                                         "sample": f"rows [0, {nrows}) of D = {dim}, {dt:.1f} s"}
+        if threads == ncores:
+            out.update({"value": rate, "unit": "states·bonds/s", "cores": used, "kind": "oracle",
+                        "sample": f"FP64 oracle H.x on rows [0, {nrows}) of the N=30 S^z=0 icosidodecahedron "
+                                  f"sector (count-based ranks, no stored basis), {dt:.1f} s, {used} threads"})
+            # the R = 2 reference run: 2 chains x 100 steps of the full sector
+            out["cases"]["ftlm_n30_R2_priced"] = {"seconds": 200 * dim * len(bonds) / rate, "threads": used,
+                                                  "sample": "200 FP64 H.x at the measured H.x rate"}
+        # N = 12 ring FTLM, whole
+        temps = oracle.log_temperatures()
+        t0, runs = time.perf_counter(), 0
+        while True:
+            oracle.ftlm(12, graphs.ring(12), [6], 8, 40, 1, oracle.PM1, temps)
+            runs += 1
+            if time.perf_counter() - t0 > 2.0:
+                break
+        dt = time.perf_counter() - t0
+        out["cases"][f"ftlm_ring12_{tag}"] = {"value": 8 * runs / dt, "unit": "samples/s", "threads": used,
+                                              "sample": f"{runs} whole runs (R=8, M=40, D=924), {dt:.1f} s"}
+        # 6x4 lattice: the H.x of the largest sector on a row range, from which
+        # the whole all-sector run is priced in proportion to rows x bonds
+        n, nu = 24, 12
+        sq = graphs.square_j1j2(6, 4, 1.0, 0.5)
+        d24 = math.comb(n, nu)
+        b24 = oracle.basis(n, nu)
+        q = np.random.default_rng(1).standard_normal(d24)
+        rows = 1 << 14
+        t0 = time.perf_counter()
+        oracle.hv(n, nu, sq, q, b24, row0=0, nrows=rows)
+        tp = time.perf_counter() - t0
+        rows = int(min(d24, max(rows, rows * 0.3 * target_s / max(tp, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.hv(n, nu, sq, q, b24, row0=0, nrows=rows)
+        dt = time.perf_counter() - t0
+        total_rows = sum(math.comb(n, k) for k in range(12, 25))
+        whole = dt / rows * 32 * 80 * total_rows
+        out["cases"][f"ftlm_square4x6_{tag}"] = {
+            "value": 416 / whole, "unit": "samples/s (extrapolated)", "threads": used,
+            "sample": f"H.x on rows [0, {rows}) of the D = {d24} sector, {dt:.1f} s; the all-sector run "
+                      f"(13 sectors, R = 32 chains of M = 80 steps) priced as {whole:.0f} s of H.x in proportion to "
+                      f"rows"}
+        del b24
+    oracle.set_threads(ncores)
+    return out
 
 
 def profile_kernels(batch=None):
@@ -409,14 +541,14 @@ def main():
     ap.add_argument("--batch", default="auto", help="chains per Lanczos batch ('auto': the autotuner's choice)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short kernel-only run for rocprofv3 counter passes")
-    ap.add_argument("--only", choices=["plan", "serving", "largest"],
+    ap.add_argument("--only", choices=["plan", "serving", "largest", "precision"],
                     help="run one secondary measurement alone and print its JSON (for kernel traces)")
     args = ap.parse_args()
     if args.profile_kernels:
         profile_kernels(None if args.batch == "auto" else int(args.batch))
         return
     if args.only:
-        run = {"plan": plan_vs_plain, "largest": largest_sector,
+        run = {"plan": plan_vs_plain, "largest": largest_sector, "precision": precision,
                "serving": lambda: serving(n_meas=args.serve_requests)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
@@ -475,6 +607,9 @@ def main():
         torch.cuda.empty_cache()
         out["largest_sector"] = largest_sector()
         log("n34", json.dumps(out["largest_sector"]))
+        torch.cuda.empty_cache()
+        out["precision"] = precision()
+        log("precision", json.dumps(out["precision"]))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

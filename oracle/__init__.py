@@ -100,6 +100,15 @@ def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data) if a is not None else ctypes.c_void_p(0)
 
 
+def set_threads(n):
+    """Thread count of the oracle's OpenMP loops (0: leave it); returns the
+    count in force."""
+    L = lib()
+    L.orc_set_threads.restype = ctypes.c_int
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    return int(L.orc_set_threads(n))
+
+
 def binom(n, k):
     """Exact C(n, k) (Eq. 15 at s = 1/2)."""
     return int(lib().orc_binom(n, k))

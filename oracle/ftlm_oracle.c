@@ -446,3 +446,11 @@ void orc_moments_stream(int n_sites, int n_up, int n_bonds, const int32_t* bi, c
         for (int k = 0; k < 3 * R; ++k) out[k] += part[ci * 3 * (uint64_t)R + (uint64_t)k];
     free(part);
 }
+
+/* Thread count of the oracle's OpenMP loops (for timing it at 1 thread and
+ * at all cores); returns the count now in force. */
+#include <omp.h>
+int orc_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}

@@ -31,6 +31,8 @@ def lib():
         L.spn_rank.argtypes = [vp, u64, u64]
         L.spn_hv.restype = None
         L.spn_hv.argtypes = [i32, i32, i32, vp, vp, vp, vp, u64, vp, vp, u64, u64]
+        L.spn_neighbors.restype = None
+        L.spn_neighbors.argtypes = [i32, i32, vp, vp, vp, u64, u64, u64, vp]
         L.spn_offdiag_count.restype = u64
         L.spn_offdiag_count.argtypes = [i32, i32, i32, i32, vp, vp]
         L._spin_sigs = True
@@ -73,6 +75,28 @@ def hv(n_sites, two_s, bonds, x, basis_arr, row0=0, nrows=None):
     lib().spn_hv(n_sites, two_s, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), _ptr(basis_arr), d, _ptr(x), _ptr(y),
                  row0, nrows)
     return y
+
+
+def neighbors(two_s, bonds, basis_arr, t0, count):
+    """[count][2 N_B] partner indices: entry 2b is the state with a_i + 1,
+    a_j - 1 for bond b = (i, j), i < j, entry 2b + 1 the one with a_i - 1,
+    a_j + 1; NONE where a digit would leave [0, 2s]."""
+    bi, bj, _ = _bonds(bonds)
+    out = np.empty((count, 2 * len(bonds)), dtype=np.uint64)
+    lib().spn_neighbors(two_s, len(bonds), _ptr(bi), _ptr(bj), _ptr(basis_arr), basis_arr.size, t0, count,
+                        _ptr(out))
+    return out
+
+
+def clt(basis_arr, n_sites, two_s):
+    """Compressed lookup table over the d^N labels (Eqs. 18-21): (mask,
+    prefix) per 32-label block, from one pass over the sorted basis."""
+    nblocks = max(1, ((two_s + 1) ** n_sites + 31) // 32)
+    mask = np.empty(nblocks, dtype=np.uint32)
+    prefix = np.empty(nblocks, dtype=np.uint32)
+    basis_arr = np.ascontiguousarray(basis_arr, dtype=np.uint64)
+    lib().orc_clt(_ptr(basis_arr), basis_arr.size, nblocks, _ptr(mask), _ptr(prefix))
+    return mask, prefix
 
 
 def offdiag_count(n_sites, two_s, a, bonds):

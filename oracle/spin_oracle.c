@@ -159,3 +159,23 @@ uint64_t spn_offdiag_count(int n_sites, int two_s, int A, int n_bonds, const int
     }
     return count;
 }
+
+/* For rows [t0, t0 + count) and each bond b = (i, j) with i < j: out[(t - t0)
+ * * 2 N_B + 2 b] = index of the state with a_i + 1, a_j - 1 and out[... + 2 b
+ * + 1] = index of the state with a_i - 1, a_j + 1 (the two ladder terms of
+ * Eq. 12), SPN_NONE where a digit would leave [0, 2s]. */
+void spn_neighbors(int two_s, int n_bonds, const int32_t* bi, const int32_t* bj, const uint64_t* basis,
+                   uint64_t dim, uint64_t t0, uint64_t count, uint64_t* out) {
+    const int d = two_s + 1;
+    for (uint64_t r = 0; r < count; ++r) {
+        const uint64_t n = basis[t0 + r];
+        for (int b = 0; b < n_bonds; ++b) {
+            const int i = bi[b] < bj[b] ? bi[b] : bj[b], j = bi[b] < bj[b] ? bj[b] : bi[b];
+            const int ai = digit(n, i, d), aj = digit(n, j, d);
+            const uint64_t di = ipow((uint64_t)d, i), dj = ipow((uint64_t)d, j);
+            uint64_t* o = out + r * (uint64_t)(2 * n_bonds) + 2 * (uint64_t)b;
+            o[0] = (ai < two_s && aj > 0) ? spn_rank(basis, dim, n + di - dj) : SPN_NONE;
+            o[1] = (ai > 0 && aj < two_s) ? spn_rank(basis, dim, n - di + dj) : SPN_NONE;
+        }
+    }
+}

@@ -148,3 +148,36 @@ def test_exact_trace_ftlm_equals_ed_spin1():
         assert abs(th["E"][k] - E) < 1e-9 * max(1, abs(E))
         assert abs(th["C"][k] - C) < 1e-8 * max(1, C)
         assert abs(th["chi"][k] - chi) < 1e-9 * max(1, chi)
+
+
+@pytest.mark.parametrize("n,two_s", [(6, 2), (4, 3), (3, 4)])
+def test_neighbor_lists_count_and_symmetry(n, two_s):
+    bonds = graphs.ring(n) if n > 3 else graphs.triangle()
+    for a in range(n * two_s + 1):
+        b = sp.basis(n, two_s, a)
+        nb = sp.neighbors(two_s, bonds, b, 0, len(b))
+        valid = nb != sp.NONE
+        # every valid term is counted once by the off-diagonal count
+        assert valid.sum() == sp.offdiag_count(n, two_s, a, bonds)
+        # symmetry: t reaches t' through term e of bond b iff t' reaches t
+        # through the opposite term of the same bond
+        for t in range(len(b)):
+            for k in np.nonzero(valid[t])[0]:
+                u = int(nb[t, k])
+                assert nb[u, k ^ 1] == t
+
+
+def test_clt_over_base_d_labels():
+    n, two_s = 5, 2
+    for a in range(n * two_s + 1):
+        b = sp.basis(n, two_s, a)
+        mask, prefix = sp.clt(b, n, two_s)
+        # Alg. 2 on every label of the space equals the rank (binary search)
+        for x in range(3 ** n):
+            blk, j = x >> 5, x & 31
+            hit = (mask[blk] >> j) & 1
+            want = sp.rank(b, [x])[0]
+            if hit:
+                assert prefix[blk] + bin(int(mask[blk]) & ((1 << j) - 1)).count("1") == want
+            else:
+                assert want == sp.NONE
