@@ -64,14 +64,27 @@ def clt_touched_bytes(n, n_up):
     return 8 * blocks
 
 
+def map_bytes(mode, dim, n, n_up):
+    """Bytes of the stored index map a launch must read at least once: the
+    basis (4 D) and the touched part of the map: the non-empty CLT blocks,
+    the D sector entries of the full table, or both Lin tables."""
+    if mode == "cr":
+        return 0
+    b = 4 * dim
+    if mode == "clt":
+        b += clt_touched_bytes(n, n_up)
+    elif mode == "full":
+        b += 4 * dim
+    elif mode == "lin":
+        lo = n // 2
+        b += 4 * ((1 << (n - lo)) + (1 << lo))
+    return b
+
+
 def hv_alg_bytes(mode, dim, nvec, n, n_up):
     """Algorithmic HBM bytes of one Lanczos-epilogue H.x launch over nvec FP32
-    columns: read x (u_k) and z (u_{k-1}), write w; CLT adds the basis and the
-    touched table blocks."""
-    b = 12 * dim * nvec
-    if mode == "clt":
-        b += 4 * dim + clt_touched_bytes(n, n_up)
-    return b
+    columns: read x (u_k) and z (u_{k-1}), write w, plus the stored map."""
+    return 12 * dim * nvec + map_bytes(mode, dim, n, n_up)
 
 
 def timed_hv(ftlm, torch, sec, g, x, y, reps):
@@ -105,7 +118,9 @@ def run_gpu(args):
     n_bonds = g.n_bonds
     temps = driver.log_temperatures()
     results = {}
-    for mode_name, mode in (("clt", ftlm.CLT), ("cr", ftlm.CR)):
+    all_modes = {"clt": ftlm.CLT, "cr": ftlm.CR, "full": ftlm.FULL, "lin": ftlm.LIN}
+    for mode_name in args.modes.split(","):
+        mode = all_modes[mode_name]
         sec = ftlm.Sector(N_SITES, N_UP, mode, device=dev)
         dim = sec.dim
         work = torch.empty(ftlm.lanczos_workspace_bytes(sec, R, ftlm.F32), dtype=torch.uint8, device=dev)
@@ -179,7 +194,7 @@ def run_gpu(args):
             x = torch.randn((dim, nv) if nv > 1 else (dim,), dtype=torch.float32, device=dev)
             y = torch.empty_like(x)
             ms = timed_hv(ftlm, torch, sec, g, x, y, 20)
-            a = hv_alg_bytes(mode_name, dim, nv, N_SITES, N_UP) - 4 * dim * nv  # no u_{k-1} read
+            a = 8 * dim * nv + map_bytes(mode_name, dim, N_SITES, N_UP)  # read x, write y, read the map
             sweep[str(nv)] = {"ms": ms, "states_bonds_per_s": dim * n_bonds * nv / (ms * 1e-3),
                               "alg_gbs": a / (ms * 1e-3) / 1e9}
             del x, y
@@ -237,7 +252,7 @@ def plan_vs_plain():
             "plain_protocol": f"one chain per launch, sector by sector, eager; {per} of {R} chains per sector timed"}
 
 
-def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True, steps_per_round=0):
+def serving(n_warm=200, n_meas=2000, rate=50.0, max_active=0, plain=True, steps_per_round=0, n_plain=200):
     """Poisson-arriving exchange-fit requests (N in 16..28, random clusters,
     J in [0.2, 1.5], one random sector, R = 16, M = 80) through the
     continuous-batching server; p50/p99 latency (arrival to result) and
@@ -278,23 +293,25 @@ def serving(n_warm=10, n_meas=60, rate=50.0, max_active=0, plain=True, steps_per
            "samples_per_s": served_sps, "peak_arena_bytes": stats["peak_bytes"], "rounds": stats["rounds"]}
     if not plain:
         return out
-    # plain FIFO: service time of each request alone with one chain per launch
+    # plain FIFO: service time of each of the first n_plain measured requests
+    # alone with one chain per launch; their FIFO latencies follow from those
+    # times and the same arrival times
     service = []
-    for q in reqs[n_warm:]:
+    for q in reqs[n_warm:n_warm + n_plain]:
         t1 = time.perf_counter()
         driver.run(q["n_sites"], q["bonds"], [q["n_up"]], q["R"], q["M"], q["seed"], ftlm.PM1, batch=1, temps=temps)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t1)
     finish, lat_plain = 0.0, []
-    for q, sv in zip(reqs[n_warm:], service):
+    for q, sv in zip(reqs[n_warm:n_warm + n_plain], service):
         finish = max(finish, q["t"]) + sv
         lat_plain.append((finish - q["t"]) * 1e3)
     plain_span = finish - reqs[n_warm]["t"]
     out.update({"plain_p50_ms": float(np.percentile(lat_plain, 50)),
                 "plain_p99_ms": float(np.percentile(lat_plain, 99)),
                 "plain_samples_per_s": 16 * len(service) / plain_span,
-                "plain_protocol": "FIFO, one request at a time, one chain per launch "
-                                  "(latencies from measured service times)"})
+                "plain_protocol": f"FIFO, one request at a time, one chain per launch; latencies of the first "
+                                  f"{len(service)} measured requests from their measured service times"})
     return out
 
 
@@ -491,7 +508,61 @@ def cpu_baseline(target_s=10.0):
                       f"rows"}
         del b24
     oracle.set_threads(ncores)
+    out["cases"].update(paper_cpu_method(target_s))
     return out
+
+
+def _mem_available_bytes():
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return 0
+
+
+def paper_cpu_method(target_s=10.0):
+    """The paper's own CPU method on the same host (Sec. 2, "Computational
+    setup": a batched B = 8 FP64 H.x with the compressed lookup table and
+    OpenMP over rows; its CPU column of Table 3): the N = 30 S^z = 0 product
+    on a row sample, at all cores and at one thread. Needs ~12 GB of host
+    memory (basis, table and an [D][8] FP64 block); skipped below that."""
+    import numpy as np
+
+    import oracle
+    from oracle import paper_cpu
+    from ftlm_inputs import graphs
+
+    dim = math.comb(N_SITES, N_UP)
+    need = dim * (8 * 8 + 8) + (1 << 25) * 8
+    if _mem_available_bytes() < 1.5 * need:
+        return {"paper_cpu_clt_b8_n30": {"skipped": f"needs ~{need / 1e9:.0f} GB of host memory"}}
+    bonds = graphs.icosidodecahedron()
+    basis = oracle.basis(N_SITES, N_UP)
+    mask, prefix = oracle.clt(basis, N_SITES)
+    x = np.empty((dim, 8), dtype=np.float64)
+    x.fill(0.5)
+    res = {}
+    ncores = len(os.sched_getaffinity(0))
+    for threads in (ncores, 1):
+        used = oracle.set_threads(threads)
+        probe = 1 << 15
+        t0 = time.perf_counter()
+        paper_cpu.hv_clt_b8(bonds, basis, mask, prefix, x, 0, probe)
+        tp = time.perf_counter() - t0
+        rows = int(min(dim, max(probe, probe * (target_s if threads > 1 else 0.5 * target_s) / max(tp, 1e-6))))
+        t0 = time.perf_counter()
+        paper_cpu.hv_clt_b8(bonds, basis, mask, prefix, x, 0, rows)
+        dt = time.perf_counter() - t0
+        res[f"paper_cpu_clt_b8_n30_{used}t"] = {
+            "value": rows * len(bonds) * 8 / dt, "unit": "states·bonds/s (8 vectors per row)", "threads": used,
+            "sample": f"rows [0, {rows}) of D = {dim}, {dt:.1f} s; the paper's CPU reference kernel "
+                      f"(batched B = 8 FP64 CLT H.x, OpenMP over rows)"}
+    oracle.set_threads(ncores)
+    del x, basis, mask, prefix
+    return res
 
 
 def profile_kernels(batch=None):
@@ -508,7 +579,7 @@ def profile_kernels(batch=None):
 
     dev = torch.device("cuda:0")
     g = ftlm.Graph(N_SITES, graphs.icosidodecahedron())
-    for mode in (ftlm.CLT, ftlm.CR):
+    for mode in (ftlm.CLT, ftlm.CR, ftlm.FULL, ftlm.LIN):
         sec = ftlm.Sector(N_SITES, N_UP, mode, device=dev)
         for B in ([batch] if batch else [w for w in LAUNCH_WIDTHS_F32 if w <= R]):
             log("profile: batch", B)
@@ -536,9 +607,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="skip the plan, serving and N=34 measurements")
-    ap.add_argument("--serve-requests", type=int, default=40,
-                    help="measured requests of the serving stream (the full stream is 2000 after 200 warm-up)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="measured requests of the serving stream (after 200 warm-up)")
     ap.add_argument("--batch", default="auto", help="chains per Lanczos batch ('auto': the autotuner's choice)")
+    ap.add_argument("--modes", default="clt,cr,full,lin",
+                    help="index maps of the headline workload (compressed table, ranking, full table, Lin)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short kernel-only run for rocprofv3 counter passes")
     ap.add_argument("--only", choices=["plan", "serving", "largest", "precision"],
@@ -549,7 +622,8 @@ def main():
         return
     if args.only:
         run = {"plan": plan_vs_plain, "largest": largest_sector, "precision": precision,
-               "serving": lambda: serving(n_meas=args.serve_requests)}[args.only]
+               "serving": lambda: serving(n_warm=200 if args.serve_requests >= 200 else 10,
+                                          n_meas=args.serve_requests)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
     if args.gpus != 1:
@@ -573,6 +647,14 @@ def main():
     counted_gbs = traffic / (dom["hv_avg_ms"] * 1e-3) / 1e9 if traffic else None
     roof["counted_gbs"] = counted_gbs
     roof["counted_frac"] = counted_gbs / HBM_PEAK_GBS if counted_gbs else None
+    # the plain H.x (ftlm_hv, no Lanczos epilogue) of the same map: one vector
+    # and the block width with the best per-vector rate
+    sweep = dom["hv_width_sweep"]
+    best_w = max(sweep, key=lambda w: sweep[w]["states_bonds_per_s"])
+    roof["plain_hv"] = {w: {"ms": sweep[w]["ms"], "achieved_gbs": sweep[w]["alg_gbs"],
+                            "frac": sweep[w]["alg_gbs"] / HBM_PEAK_GBS,
+                            "states_bonds_per_s": sweep[w]["states_bonds_per_s"]}
+                        for w in sorted({"1", best_w}, key=int)}
     out = {
         "metric": METRIC,
         "value": r["states_bonds_per_s"],
@@ -601,8 +683,7 @@ def main():
         out["batched_all_sector"] = plan_vs_plain()
         log("plan", json.dumps(out["batched_all_sector"]))
         torch.cuda.empty_cache()
-        n_warm = 200 if args.serve_requests >= 2000 else 10
-        out["serving"] = serving(n_warm=n_warm, n_meas=args.serve_requests)
+        out["serving"] = serving(n_warm=200 if args.serve_requests >= 200 else 10, n_meas=args.serve_requests)
         log("serving", json.dumps(out["serving"]))
         torch.cuda.empty_cache()
         out["largest_sector"] = largest_sector()

@@ -60,6 +60,13 @@ extern "C" {
 /* ---- enumerations ------------------------------------------------------ */
 #define FTLM_CLT 0   /* compressed lookup table indexing (Sec. 2, Eqs. 18-21, Alg. 2) */
 #define FTLM_CR 1    /* combinatorial ranking, no per-label table (Sec. 2, Eqs. 15-17, Alg. 1) */
+#define FTLM_FULL 2  /* full lookup table: one uint32 index per label of [0, 2^N) (Sec. 2,
+                        "State-to-index mapping"); 4 * 2^N bytes */
+#define FTLM_LIN 3   /* Lin's two-dimensional search (Sec. 2, "State-to-index mapping"): the
+                        label split into a high part h and a low part l of L = floor(N/2)
+                        bits; index = hi[h] + lo[l], hi[h] the number of sector labels with
+                        a smaller high part, lo[l] the rank of l among the L-bit strings with
+                        its popcount; 4 (2^(N-L) + 2^L) bytes */
 
 #define FTLM_F32 0
 #define FTLM_F64 1
@@ -103,13 +110,14 @@ int ftlm_graph_n_bonds(const ftlm_graph* g);
  * FTLM_E_INVALID for n_up outside [0, N]. */
 int ftlm_sector_info(int n_sites, int n_up, uint64_t* dim, double* mult);
 
-/* ftlm_sector_table_bytes: device bytes the sector tables need. Both modes
- * hold a binomial table C(p, k) (the cumulative dimension table D_c(p, A, 1)
- * of Eq. 16 at s = 1/2, a few KB). FTLM_CLT adds the sorted basis (uint32
- * per state, N <= 32) and the compressed lookup table: one {mask, prefix}
- * pair of uint32 per block of 32 labels over [0, 2^N) (Eqs. 18-21; 8 bytes
- * per block, Eq. 21). FTLM_CR stores nothing per label (Sec. 2, CR).
- * Errors: FTLM_E_RANGE when N > 64, D >= 2^32, or N > 32 in FTLM_CLT mode. */
+/* ftlm_sector_table_bytes: device bytes the sector tables need. Every mode
+ * holds a binomial table C(p, k) (the cumulative dimension table D_c(p, A, 1)
+ * of Eq. 16 at s = 1/2, a few KB). FTLM_CR stores nothing per label (Sec. 2,
+ * CR). The stored maps add the sorted basis (uint32 per state, N <= 32) and:
+ * FTLM_CLT the compressed lookup table, one {mask, prefix} pair of uint32 per
+ * block of 32 labels over [0, 2^N) (Eqs. 18-21; 8 bytes per block, Eq. 21);
+ * FTLM_FULL a uint32 per label of [0, 2^N); FTLM_LIN the two half tables.
+ * Errors: FTLM_E_RANGE when N > 64, D >= 2^32, or N > 32 for a stored map. */
 int ftlm_sector_table_bytes(int n_sites, int n_up, int mode, size_t* bytes);
 
 /* ftlm_sector_create: builds the tables into the caller's device buffer
@@ -124,6 +132,33 @@ int ftlm_sector_create(int n_sites, int n_up, int mode, void* table_dev, size_t 
 uint64_t ftlm_sector_dim(const ftlm_sector* s);
 int ftlm_sector_mode(const ftlm_sector* s);
 void ftlm_sector_destroy(ftlm_sector* s);
+
+/* ---- general local spin s (Sec. 2, Eqs. 11-17) --------------------------------
+ * two_s = 2s in [1, 7] (d = 2s + 1 states per site), 2 <= N <= 16. A basis
+ * state is the base-d integer n = sum_k a_k d^k with digit a_k = m_k + s
+ * (Eq. 11); the sector is the set of labels with digit sum a_tot = N s + M
+ * (Eq. 17), ordered by increasing label, of dimension D(N, a_tot) from the
+ * recursion of Eq. (15). two_s = 1 is the spin-1/2 case (a_tot = n_up; these
+ * calls then act as the ones above). A general-spin sector works with every
+ * call that takes a sector except the plans and the server, which hold
+ * spin-1/2 sectors:
+ *   - ftlm_rank / ftlm_unrank take and return base-d labels (FTLM_NONE for a
+ *     label outside the sector or at or above d^N);
+ *   - ftlm_neighbors writes 2 * n_bonds entries per row (below);
+ *   - ftlm_hv, ftlm_hv_rows, ftlm_start_vectors, ftlm_lanczos and
+ *     ftlm_autotune run the same algorithms with launches of at most 8
+ *     columns; start-vector streams are keyed by (seed, a_tot, r);
+ *   - H = sum_b J_b (S_i^z S_j^z + (S_i^+ S_j^- + S_i^- S_j^+) / 2), the
+ *     ladder terms with the coefficients of Eqs. (13)-(14).
+ * Table: FTLM_CR stores the cumulative dimension table D_c of Eq. (16)
+ * (N (a_tot + 3) (2s + 1) uint32); FTLM_CLT adds the basis (uint32[D]) and
+ * the compressed lookup table over all d^N labels (Eqs. 18-21; needs d^N <=
+ * 2^32). D must be < 2^32. Errors as for the spin-1/2 calls. */
+int ftlm_sector_info_spin(int n_sites, int two_s, int a_tot, uint64_t* dim, double* mult);
+int ftlm_sector_table_bytes_spin(int n_sites, int two_s, int a_tot, int mode, size_t* bytes);
+int ftlm_sector_create_spin(int n_sites, int two_s, int a_tot, int mode, void* table_dev, size_t bytes,
+                            void* stream, ftlm_sector** out);
+int ftlm_sector_two_s(const ftlm_sector* s);
 
 /* ftlm_rank: idx_dev[i] = sector index of labels_dev[i], FTLM_NONE when the
  * label is not in the sector. Mode FTLM_CLT looks up the table (Alg. 2);
@@ -152,7 +187,12 @@ int ftlm_clt_export(const ftlm_sector* s, uint32_t* mask_host, uint32_t* prefix_
  * of the partner label n_t XOR (2^i + 2^j) when sites i, j of bond b are
  * antiparallel in n_t, else FTLM_NONE (Eq. 12 at s = 1/2; Eqs. 13-14 give the
  * coefficient J_b / 2). The indices come from the same code the H.x kernels
- * use. idx_dev is device uint64[count * n_bonds]. Test hook. */
+ * use. idx_dev is device uint64[count * n_bonds]. For a general-spin sector
+ * each bond b = (i, j), i < j, has two entries: idx_dev[(t - t0) * 2 n_bonds
+ * + 2 b] is the index of the source state with a_i + 1, a_j - 1 and entry
+ * 2 b + 1 the one with a_i - 1, a_j + 1 (the two ladder terms of Eq. 12), or
+ * FTLM_NONE where the digit leaves [0, 2s]; idx_dev then holds count * 2 *
+ * n_bonds entries. Test hook. */
 int ftlm_neighbors(const ftlm_sector* s, const ftlm_graph* g, uint64_t t0, uint64_t count,
                    uint64_t* idx_dev, void* stream);
 
@@ -409,10 +449,10 @@ int ftlm_ritz_batch(int n, int stride, const int32_t* m, const double* alpha, co
 /* One sector's Lanczos samples for ftlm_thermo. theta and weight are
  * [R][stride] host arrays; sample r uses its first steps[r] entries. */
 typedef struct ftlm_sector_result {
-    int32_t n_up;
+    int32_t n_up;        /* digit sum A of the sector (the up-spin count at s = 1/2) */
     int32_t R;
     int32_t stride;
-    int32_t reserved;
+    int32_t two_s;       /* 2s of the local spin; 0 or 1 for spin 1/2. M = A - N s (Eq. 17) */
     uint64_t dim;        /* D_Gamma */
     double mult;         /* 1 for M = 0, 2 for M > 0 (sectors -M mirror +M, Sec. 2) */
     const double* theta;

@@ -6,7 +6,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "ftlm_oracle.c"), os.path.join(HERE, "spin_oracle.c")]
+SRCS = [os.path.join(HERE, "ftlm_oracle.c"), os.path.join(HERE, "spin_oracle.c"), os.path.join(HERE, "paper_cpu.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

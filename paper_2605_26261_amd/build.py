@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libftlm.so")
 SOURCES = ["abi.cpp", "host.cpp", "server.cpp", "host_math.cpp", "bonds.cpp", "sector.hip", "hv_f32.hip", "hv_f64.hip",
-           "lanczos.hip", "noalloc.hip"]
+           "lanczos.hip", "noalloc.hip", "hv_spin.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

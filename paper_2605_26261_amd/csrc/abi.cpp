@@ -81,11 +81,12 @@ int ftlm_sector_info(int n_sites, int n_up, uint64_t* dim, double* mult) {
 
 int ftlm_sector_table_bytes(int n_sites, int n_up, int mode, size_t* bytes) {
     if (!bytes) return fail(FTLM_E_INVALID, "null argument");
-    if (mode != FTLM_CLT && mode != FTLM_CR) return fail(FTLM_E_INVALID, "mode %d is not FTLM_CLT/FTLM_CR", mode);
+    if (mode != FTLM_CLT && mode != FTLM_CR && mode != FTLM_FULL && mode != FTLM_LIN)
+        return fail(FTLM_E_INVALID, "mode %d is not FTLM_CLT/FTLM_CR/FTLM_FULL/FTLM_LIN", mode);
     if (n_sites < 1 || n_sites > kMaxSites) return fail(FTLM_E_RANGE, "n_sites %d not in [1, %d]", n_sites, kMaxSites);
     if (n_up < 0 || n_up > n_sites) return fail(FTLM_E_INVALID, "n_up %d not in [0, %d]", n_up, n_sites);
-    if (mode == FTLM_CLT && n_sites > kMaxCltSites)
-        return fail(FTLM_E_RANGE, "FTLM_CLT holds uint32 labels: n_sites %d > %d", n_sites, kMaxCltSites);
+    if (mode != FTLM_CR && n_sites > kMaxCltSites)
+        return fail(FTLM_E_RANGE, "stored maps hold uint32 labels: n_sites %d > %d", n_sites, kMaxCltSites);
     const uint64_t dim = binom_u64(n_sites, n_up);
     if (dim >= (uint64_t(1) << 32)) return fail(FTLM_E_RANGE, "sector dimension %llu >= 2^32", (unsigned long long)dim);
     *bytes = table_layout(n_sites, n_up, mode, dim).total;
@@ -122,14 +123,22 @@ int ftlm_sector_create(int n_sites, int n_up, int mode, void* table_dev, size_t 
     d.bw = w;
     d.dim = uint32_t(s->dim);
     d.binom = at<uint32_t>(table_dev, s->layout.binom_off);
-    d.basis = mode == FTLM_CLT ? at<uint32_t>(table_dev, s->layout.basis_off) : nullptr;
+    d.basis = mode != FTLM_CR ? at<uint32_t>(table_dev, s->layout.basis_off) : nullptr;
     d.clt = mode == FTLM_CLT ? at<CltEntry>(table_dev, s->layout.clt_off) : nullptr;
+    d.full = mode == FTLM_FULL ? at<uint32_t>(table_dev, s->layout.full_off) : nullptr;
+    d.lin_hi = mode == FTLM_LIN ? at<uint32_t>(table_dev, s->layout.hi_off) : nullptr;
+    d.lin_lo = mode == FTLM_LIN ? at<uint32_t>(table_dev, s->layout.lo_off) : nullptr;
+    d.lin_lo_bits = lin_low_bits(n_sites);
+    d.two_s = 1;
+    d.n_labels = n_sites < 64 ? (uint64_t(1) << n_sites) : ~uint64_t(0);
     hipError_t e = hipMemcpyAsync(const_cast<uint32_t*>(d.binom), s->binom_host.data(),
                                   s->binom_host.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host copy may be reused at once
-    if (e == hipSuccess && mode == FTLM_CLT) {
+    if (e == hipSuccess && mode != FTLM_CR) {
         e = launch_build_basis(d, st);
-        if (e == hipSuccess) e = launch_build_clt(d, st);
+        if (e == hipSuccess && mode == FTLM_CLT) e = launch_build_clt(d, st);
+        if (e == hipSuccess && mode == FTLM_FULL) e = launch_build_full(d, st);
+        if (e == hipSuccess && mode == FTLM_LIN) e = launch_build_lin(d, st);
     }
     if (e != hipSuccess) {
         delete s;
@@ -143,17 +152,148 @@ uint64_t ftlm_sector_dim(const ftlm_sector* s) { return s ? s->dim : 0; }
 int ftlm_sector_mode(const ftlm_sector* s) { return s ? s->mode : -1; }
 void ftlm_sector_destroy(ftlm_sector* s) { delete s; }
 
+// ---- general local spin (Sec. 2, Eqs. 11-17) ---------------------------------------
+}  // extern "C"
+
+namespace {
+
+// D(m, A) for 0 <= m <= N, 0 <= A <= N two_s by the recursion of Eq. (15);
+// exact in 64 bits for every size accepted here (D <= d^N <= 8^16).
+std::vector<std::vector<uint64_t>> spin_dims(int n_sites, int two_s) {
+    const int amax = n_sites * two_s;
+    std::vector<std::vector<uint64_t>> D(size_t(n_sites) + 1, std::vector<uint64_t>(size_t(amax) + 1, 0));
+    D[0][0] = 1;
+    for (int m = 1; m <= n_sites; ++m)
+        for (int a = 0; a <= m * two_s; ++a)
+            for (int q = 0; q <= two_s && q <= a; ++q) D[size_t(m)][size_t(a)] += D[size_t(m - 1)][size_t(a - q)];
+    return D;
+}
+
+uint64_t ipow_u64(uint64_t b, int e) {
+    uint64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+int check_spin_args(int n_sites, int two_s, int a_tot, int mode) {
+    if (mode != FTLM_CLT && mode != FTLM_CR)
+        return fail(FTLM_E_INVALID, "mode %d: general spin takes FTLM_CLT or FTLM_CR", mode);
+    if (two_s < 1 || two_s > 7) return fail(FTLM_E_RANGE, "2s = %d not in [1, 7]", two_s);
+    if (n_sites < 2 || n_sites > 16) return fail(FTLM_E_RANGE, "n_sites %d not in [2, 16] for general spin", n_sites);
+    if (a_tot < 0 || a_tot > n_sites * two_s)
+        return fail(FTLM_E_INVALID, "digit sum %d not in [0, %d]", a_tot, n_sites * two_s);
+    return FTLM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ftlm_sector_info_spin(int n_sites, int two_s, int a_tot, uint64_t* dim, double* mult) {
+    if (two_s == 1) return ftlm_sector_info(n_sites, a_tot, dim, mult);
+    if (int rc = check_spin_args(n_sites, two_s, a_tot, FTLM_CR)) return rc;
+    if (dim) *dim = spin_dims(n_sites, two_s)[size_t(n_sites)][size_t(a_tot)];
+    if (mult) *mult = 2 * a_tot == n_sites * two_s ? 1.0 : 2.0;
+    return ok();
+}
+
+int ftlm_sector_table_bytes_spin(int n_sites, int two_s, int a_tot, int mode, size_t* bytes) {
+    if (!bytes) return fail(FTLM_E_INVALID, "null argument");
+    if (two_s == 1) return ftlm_sector_table_bytes(n_sites, a_tot, mode, bytes);
+    if (int rc = check_spin_args(n_sites, two_s, a_tot, mode)) return rc;
+    const uint64_t dim = spin_dims(n_sites, two_s)[size_t(n_sites)][size_t(a_tot)];
+    if (dim >= (uint64_t(1) << 32)) return fail(FTLM_E_RANGE, "sector dimension %llu >= 2^32", (unsigned long long)dim);
+    const uint64_t labels = ipow_u64(uint64_t(two_s + 1), n_sites);
+    if (mode == FTLM_CLT && labels > (uint64_t(1) << 32))
+        return fail(FTLM_E_RANGE, "FTLM_CLT holds uint32 labels: d^N = %llu > 2^32", (unsigned long long)labels);
+    size_t end = align256(size_t(n_sites) * size_t(a_tot + 3) * size_t(two_s + 1) * 4);
+    if (mode == FTLM_CLT) {
+        end = align256(end + size_t(dim) * 4);
+        end = align256(end + size_t((labels + 31) / 32) * sizeof(CltEntry));
+    }
+    *bytes = end;
+    return ok();
+}
+
+int ftlm_sector_create_spin(int n_sites, int two_s, int a_tot, int mode, void* table_dev, size_t bytes,
+                            void* stream, ftlm_sector** out) {
+    if (!out || !table_dev) return fail(FTLM_E_INVALID, "null argument");
+    if (two_s == 1) return ftlm_sector_create(n_sites, a_tot, mode, table_dev, bytes, stream, out);
+    *out = nullptr;
+    size_t need = 0;
+    if (int rc = ftlm_sector_table_bytes_spin(n_sites, two_s, a_tot, mode, &need)) return rc;
+    if (bytes < need) return fail(FTLM_E_NOSPACE, "table buffer holds %zu bytes, %zu needed", bytes, need);
+    if (reinterpret_cast<uintptr_t>(table_dev) % 256 != 0) return fail(FTLM_E_INVALID, "table buffer not 256-byte aligned");
+    const auto D = spin_dims(n_sites, two_s);
+    const int d = two_s + 1, bw = a_tot + 3;
+    ftlm_sector* s = new ftlm_sector();
+    s->n_sites = n_sites;
+    s->n_up = a_tot;
+    s->two_s = two_s;
+    s->mode = mode;
+    s->dim = D[size_t(n_sites)][size_t(a_tot)];
+    s->table = table_dev;
+    s->bytes = bytes;
+    // D_c(p, A, a) = sum_{q < a} D(p, A - q) (Eq. 16) for A in [-1, a_tot + 1], mod 2^32
+    s->binom_host.assign(size_t(n_sites) * size_t(bw) * size_t(d), 0u);
+    for (int p = 0; p < n_sites; ++p)
+        for (int A = -1; A <= a_tot + 1; ++A)
+            for (int a = 0; a < d; ++a) {
+                uint64_t c = 0;
+                for (int q = 0; q < a; ++q) {
+                    const int r = A - q;
+                    if (r >= 0 && r <= p * two_s) c += D[size_t(p)][size_t(r)];
+                }
+                s->binom_host[(size_t(p) * size_t(bw) + size_t(A + 1)) * size_t(d) + size_t(a)] = uint32_t(c);
+            }
+    const uint64_t labels = ipow_u64(uint64_t(d), n_sites);
+    const size_t tab_end = align256(s->binom_host.size() * 4);
+    SectorDev& dv = s->dev;
+    dv.n_sites = n_sites;
+    dv.n_up = a_tot;
+    dv.mode = mode;
+    dv.bw = bw;
+    dv.dim = uint32_t(s->dim);
+    dv.binom = static_cast<const uint32_t*>(table_dev);
+    dv.basis = mode == FTLM_CLT ? at<uint32_t>(table_dev, tab_end) : nullptr;
+    dv.clt = mode == FTLM_CLT ? at<CltEntry>(table_dev, align256(tab_end + size_t(s->dim) * 4)) : nullptr;
+    dv.two_s = two_s;
+    dv.n_labels = labels;
+    s->layout.binom_off = 0;
+    s->layout.basis_off = mode == FTLM_CLT ? tab_end : 0;
+    s->layout.clt_off = mode == FTLM_CLT ? align256(tab_end + size_t(s->dim) * 4) : 0;
+    s->layout.total = need;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(const_cast<uint32_t*>(dv.binom), s->binom_host.data(), s->binom_host.size() * 4,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host copy may be reused at once
+    if (e == hipSuccess && mode == FTLM_CLT) {
+        e = launch_build_basis_spin(dv, st);
+        if (e == hipSuccess) e = launch_build_clt_spin(dv, st);
+    }
+    if (e != hipSuccess) {
+        delete s;
+        return fail(FTLM_E_DEVICE, "sector build: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return ok();
+}
+
+int ftlm_sector_two_s(const ftlm_sector* s) { return s ? s->two_s : 0; }
+
 int ftlm_rank(const ftlm_sector* s, const uint64_t* labels_dev, uint64_t* idx_dev, uint64_t n, void* stream) {
     if (!s || (n && (!labels_dev || !idx_dev))) return fail(FTLM_E_INVALID, "null argument");
     if (n == 0) return ok();
-    HIP_CHECK(launch_rank(s->dev, labels_dev, idx_dev, n, static_cast<hipStream_t>(stream)));
+    if (s->two_s > 1) HIP_CHECK(launch_rank_spin(s->dev, labels_dev, idx_dev, n, static_cast<hipStream_t>(stream)));
+    else HIP_CHECK(launch_rank(s->dev, labels_dev, idx_dev, n, static_cast<hipStream_t>(stream)));
     return ok();
 }
 
 int ftlm_unrank(const ftlm_sector* s, const uint64_t* idx_dev, uint64_t* labels_dev, uint64_t n, void* stream) {
     if (!s || (n && (!labels_dev || !idx_dev))) return fail(FTLM_E_INVALID, "null argument");
     if (n == 0) return ok();
-    HIP_CHECK(launch_unrank(s->dev, idx_dev, labels_dev, n, static_cast<hipStream_t>(stream)));
+    if (s->two_s > 1) HIP_CHECK(launch_unrank_spin(s->dev, idx_dev, labels_dev, n, static_cast<hipStream_t>(stream)));
+    else HIP_CHECK(launch_unrank(s->dev, idx_dev, labels_dev, n, static_cast<hipStream_t>(stream)));
     return ok();
 }
 
@@ -161,8 +301,9 @@ int ftlm_clt_export(const ftlm_sector* s, uint32_t* mask_host, uint32_t* prefix_
                     void* stream) {
     if (!s || !mask_host || !prefix_host) return fail(FTLM_E_INVALID, "null argument");
     if (s->mode != FTLM_CLT) return fail(FTLM_E_INVALID, "sector is not in FTLM_CLT mode");
-    if (nblocks > clt_blocks(s->n_sites)) return fail(FTLM_E_RANGE, "nblocks %llu > %llu", (unsigned long long)nblocks,
-                                                     (unsigned long long)clt_blocks(s->n_sites));
+    const uint64_t have = s->two_s > 1 ? (s->dev.n_labels + 31) / 32 : clt_blocks(s->n_sites);
+    if (nblocks > have) return fail(FTLM_E_RANGE, "nblocks %llu > %llu", (unsigned long long)nblocks,
+                                    (unsigned long long)have);
     std::vector<CltEntry> tmp(static_cast<size_t>(nblocks));
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_CHECK(hipMemcpyAsync(tmp.data(), s->dev.clt, size_t(nblocks) * sizeof(CltEntry), hipMemcpyDeviceToHost, st));
@@ -181,7 +322,9 @@ int ftlm_neighbors(const ftlm_sector* s, const ftlm_graph* g, uint64_t t0, uint6
     if (t0 > s->dim || count > s->dim - t0) return fail(FTLM_E_RANGE, "rows [%llu, +%llu) outside the sector",
                                                         (unsigned long long)t0, (unsigned long long)count);
     if (count == 0) return ok();
-    HIP_CHECK(launch_neighbors(s->dev, g->table, t0, count, idx_dev, static_cast<hipStream_t>(stream)));
+    if (s->two_s > 1)
+        HIP_CHECK(launch_neighbors_spin(s->dev, g->table, t0, count, idx_dev, static_cast<hipStream_t>(stream)));
+    else HIP_CHECK(launch_neighbors(s->dev, g->table, t0, count, idx_dev, static_cast<hipStream_t>(stream)));
     return ok();
 }
 
@@ -207,7 +350,7 @@ int ftlm_hv_rows(const ftlm_sector* s, const ftlm_graph* g, const void* x_dev, v
     h.nrows = uint32_t(nrows);
     h.dtype = dtype;
     h.grid = int(rows_grid(uint32_t(nrows)));
-    for (auto [col, vb] : column_chunks(nvec, uint64_t(nvec), dtype, {x_dev, y_dev})) {
+    for (auto [col, vb] : column_chunks(nvec, uint64_t(nvec), dtype, {x_dev, y_dev}, max_launch_width(s->two_s))) {
         h.col0 = uint32_t(col);
         h.vb = vb;
         HvTimer timer(st);
@@ -231,7 +374,7 @@ namespace {
 
 struct SingleLayout {
     SectorState st;
-    size_t secs, bonds, total;
+    size_t secs, bonds, queue, total;
 };
 
 SingleLayout single_layout(uint64_t dim, int R, int dtype) {
@@ -241,6 +384,8 @@ SingleLayout single_layout(uint64_t dim, int R, int dtype) {
     off = align256(off + sizeof(SecWork));
     l.bonds = off;
     off = align256(off + kTablesPerGraph * sizeof(BondTable));
+    l.queue = off;
+    off = align256(off + kQueueBytes);
     l.total = off;
     return l;
 }
@@ -260,6 +405,7 @@ void single_job(LanczosJob& job, const ftlm_sector* s, const ftlm_graph* g, int 
     const SingleLayout l = single_layout(s->dim, R, dtype);
     job_layout(job, {s->dev}, {l.st}, work, R, M, dtype, at<SecWork>(work, l.secs), {g},
                {at<BondTable>(work, l.bonds)}, {0});
+    job.queue = at<uint32_t>(work, l.queue);
 }
 
 }  // namespace
@@ -379,11 +525,12 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
     // every width a Lanczos launch can take (FP32 only: 10, 12, 20, 32), so
     // that a batch of any size is priced from launches that were measured
     const int widths[] = {1, 2, 4, 8, 10, 12, 16, 20, 32};
+    const int widest = max_launch_width(s->two_s);
     EventPair ev;
     HIP_CHECK(ev.create());
     int n = 0;
     for (int B : widths) {
-        if (B > R || (dtype == FTLM_F64 && (B > 16 || B == 10 || B == 12))) continue;
+        if (B > R || B > widest || (dtype == FTLM_F64 && (B > 16 || B == 10 || B == 12))) continue;
         // B chains of the sector (their state fits the workspace sized for
         // R >= B); two Lanczos steps per repetition, the first one a warm-up
         LanczosJob job;
@@ -414,7 +561,7 @@ int ftlm_autotune(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype, v
     };
     auto batch_ms = [&](int x) {
         double t = 0.0;
-        for (auto [col, w] : column_chunks_v(x, uint64_t(x), dtype, {})) t += measured(w);
+        for (auto [col, w] : column_chunks_v(x, uint64_t(x), dtype, {}, widest)) t += measured(w);
         return t;
     };
     // R chains in batches of b: R / b full batches and one of R mod b
@@ -465,7 +612,7 @@ namespace {
 // Arena of a plan: the sector descriptors, then per sector its tables and its
 // Lanczos state.
 struct PlanLayout {
-    size_t secs, bonds;
+    size_t secs, bonds, queue;
     std::vector<size_t> table;
     std::vector<size_t> table_bytes;
     std::vector<SectorState> state;
@@ -479,6 +626,8 @@ int plan_layout(int n_sites, int n_sectors, const int32_t* n_ups, int mode, int 
     off = align256(off + size_t(n_sectors) * sizeof(SecWork));
     L.bonds = off;
     off = align256(off + kTablesPerGraph * sizeof(BondTable));
+    L.queue = off;
+    off = align256(off + kQueueBytes);
     for (int i = 0; i < n_sectors; ++i) {
         size_t tb = 0;
         if (int rc = ftlm_sector_table_bytes(n_sites, n_ups[i], mode, &tb)) return rc;
@@ -554,6 +703,7 @@ int ftlm_plan_create(const ftlm_graph* g, int n_sectors, const int32_t* n_ups, i
     }
     job_layout(p->job, devs, L.state, arena_dev, R, M, dtype, at<SecWork>(arena_dev, L.secs), {g},
                {at<BondTable>(arena_dev, L.bonds)}, std::vector<int>(size_t(n_sectors), 0));
+    p->job.queue = at<uint32_t>(arena_dev, L.queue);
     hipError_t e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ready, hipEventDisableTiming);
@@ -704,7 +854,9 @@ int ftlm_thermo(int n_sites, int n_sectors, const ftlm_sector_result* sectors, i
         if (r.R < 1 || !r.theta || !r.weight || !r.steps || r.stride < 1) return fail(FTLM_E_INVALID, "sector %d malformed", i);
         for (int k = 0; k < r.R; ++k)
             if (r.steps[k] < 1 || r.steps[k] > r.stride) return fail(FTLM_E_INVALID, "sector %d sample %d steps", i, k);
-        v[size_t(i)] = SectorSamples{r.n_up, r.R, r.stride, r.dim, r.mult, r.theta, r.weight, r.steps};
+        if (r.two_s < 0 || r.two_s > 7) return fail(FTLM_E_INVALID, "sector %d: 2s = %d", i, r.two_s);
+        v[size_t(i)] = SectorSamples{r.n_up, r.two_s > 1 ? r.two_s : 1, r.R, r.stride, r.dim, r.mult,
+                                     r.theta, r.weight, r.steps};
     }
     for (int i = 0; i < nT; ++i)
         if (!(T[i] > 0.0)) return fail(FTLM_E_INVALID, "temperature %d not positive", i);

@@ -125,37 +125,83 @@ struct BondTable {
     __device__ __forceinline__ uint32_t orig(int b) const { return pack[b] >> 16; }
 };
 
+// Partner-index maps that keep a stored table, read in two phases so that a
+// group of lookups is in flight together: fetch(m) issues the table loads of
+// label m, index(e, m) turns them into the sector index.
+//   CLT (Alg. 2): one 8-byte {mask, prefix} load and a popcount;
+//   FULL (the full lookup table of Sec. 2): one 4-byte load of the index;
+//   LIN (Lin's two-dimensional search, Sec. 2): the number of sector labels
+//   whose high part (label >> L) is smaller, plus the rank of the low part
+//   among L-bit strings with its popcount: two 4-byte loads and an add.
+template <int MODE>
+struct TableMap;
+
+template <>
+struct TableMap<kModeClt> {
+    using Entry = CltEntry;
+    const CltEntry* clt;
+    __device__ __forceinline__ Entry none() const { return CltEntry{0u, 0u}; }
+    __device__ __forceinline__ Entry fetch(uint32_t m) const { return clt_entry(clt, m >> 5); }
+    __device__ __forceinline__ uint32_t index(const Entry& e, uint32_t m) const {
+        return e.prefix + __popc(e.mask & ((1u << (m & 31u)) - 1u));
+    }
+};
+
+template <>
+struct TableMap<kModeFull> {
+    using Entry = uint32_t;
+    const uint32_t* full;
+    __device__ __forceinline__ Entry none() const { return 0u; }
+    __device__ __forceinline__ Entry fetch(uint32_t m) const { return *gptr(full + m); }
+    __device__ __forceinline__ uint32_t index(const Entry& e, uint32_t) const { return e; }
+};
+
+template <>
+struct TableMap<kModeLin> {
+    struct Entry {
+        uint32_t hi, lo;
+    };
+    const uint32_t* hi_tab;
+    const uint32_t* lo_tab;
+    int lo_bits;
+    __device__ __forceinline__ Entry none() const { return Entry{0u, 0u}; }
+    __device__ __forceinline__ Entry fetch(uint32_t m) const {
+        return Entry{*gptr(hi_tab + (m >> lo_bits)), *gptr(lo_tab + (m & ((1u << lo_bits) - 1u)))};
+    }
+    __device__ __forceinline__ uint32_t index(const Entry& e, uint32_t) const { return e.hi + e.lo; }
+};
+
 // Reports every bond of the row with label n to the visitor, the partner
-// indices found with Alg. 2 (the occupancy test always passes for a flip
-// inside the sector, Sec. 2):
+// indices found through a stored map (the occupancy test always passes for a
+// flip inside the sector, Sec. 2):
 //   v.flip(b, idx)  for an antiparallel bond b (b in the sorted order), and
 //   v.par(b)        for a parallel one;
 // or, when the visitor takes groups (V::kGroup > 1), v.group(b0, idx, flips)
-// for kGroup consecutive bonds at a time (CLT). In CR (cr_bonds below) a
+// for kGroup consecutive bonds at a time. In CR (cr_bonds below) a
 // visitor takes up to V::kSiteGroup bonds of one lower site at a time, as
-// v.issue(b0, idx, flips, count) (two groups in flight, V::kPipe) or
-// v.site_group(b0, idx, flips, count). A group's table loads and then its row
+// v.site_group(b0, idx, flips, count); cr_bonds_pairs keeps two such slots
+// in flight. A group's table loads and then its row
 // gathers are in flight together; lanes whose bond is parallel issue neither,
 // and the visitor weighs them by zero.
-template <typename V>
-__device__ __forceinline__ void clt_bonds(uint32_t n, const BondTable& B, const CltEntry* __restrict__ clt, V& v) {
+template <typename Map, typename V>
+__device__ __forceinline__ void table_bonds(uint32_t n, const BondTable& B, const Map& map, V& v) {
     int b = 0;
     constexpr int G = V::kGroup;
     if constexpr (G > 1) {
         for (; b + G <= B.n_bonds; b += G) {
             uint32_t m[G], idx[G];
             bool anti[G];
-            CltEntry e[G];
+            typename Map::Entry e[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const uint32_t lo = B.lo(b + g), hi = B.hi(b + g);
                 anti[g] = ((n >> lo) & 1u) != ((n >> hi) & 1u);
                 m[g] = n ^ ((1u << lo) | (1u << hi));
-                e[g] = CltEntry{0u, 0u};
-                if (anti[g]) e[g] = clt_entry(clt, m[g] >> 5);
+                e[g] = map.none();
+                if (anti[g]) e[g] = map.fetch(m[g]);
             }
 #pragma unroll
-            for (int g = 0; g < G; ++g) idx[g] = e[g].prefix + __popc(e[g].mask & ((1u << (m[g] & 31u)) - 1u));
+            for (int g = 0; g < G; ++g) idx[g] = map.index(e[g], m[g]);
             v.group(b, idx, anti);
         }
     }
@@ -163,8 +209,7 @@ __device__ __forceinline__ void clt_bonds(uint32_t n, const BondTable& B, const 
         const uint32_t si = (n >> B.lo(b)) & 1u, sj = (n >> B.hi(b)) & 1u;
         if (si != sj) {
             const uint32_t m = n ^ ((1u << B.lo(b)) | (1u << B.hi(b)));
-            const CltEntry e = clt_entry(clt, m >> 5);
-            v.flip(b, e.prefix + __popc(e.mask & ((1u << (m & 31u)) - 1u)));
+            v.flip(b, map.index(map.fetch(m), m));
         } else {
             v.par(b);
         }
@@ -212,28 +257,7 @@ __device__ __forceinline__ L cr_bonds(uint32_t t, L n_in, int n_up, const BondTa
         }
         ylds[p * 64] = Y;
         const int end = int(B.ends[p]);
-        if constexpr (V::kPipe) {
-            // the bonds whose lower site is p, V::kSiteGroup at a time, issued
-            // before the previous group is accumulated
-            constexpr int G = V::kSiteGroup;
-            for (; b < end; b += G) {
-                const int cnt = end - b < G ? end - b : G;
-                uint32_t idx[G];
-                bool anti[G];
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    anti[g] = false;
-                    idx[g] = t;
-                    if (g < cnt) {
-                        const uint32_t hb = B.hi(b + g);
-                        anti[g] = uint32_t((n >> hb) & 1) != uint32_t(one);
-                        if (anti[g]) idx[g] = t + X + ylds[hb * 64];
-                    }
-                }
-                v.issue(b, idx, anti, cnt);
-            }
-            b = end;
-        } else if constexpr (V::kSiteGroup > 1) {
+        if constexpr (V::kSiteGroup > 1) {
             // the bonds whose lower site is p, V::kSiteGroup at a time: their
             // gathers go out together before any of them is consumed
             constexpr int G = V::kSiteGroup;
@@ -263,25 +287,101 @@ __device__ __forceinline__ L cr_bonds(uint32_t t, L n_in, int n_up, const BondTa
             }
         }
     }
-    if constexpr (V::kPipe) v.finish();
+    return n;
+}
+
+// cr_bonds for a visitor that keeps two slots of row gathers in flight
+// (V::kPairs): the bonds, in their sorted order, are taken kSiteGroup at a
+// time into slot A and slot B in turn, and each slot is accumulated after the
+// other slot's next loads have been issued. The two slots are fixed registers
+// (the loop body handles one A and one B) loaded by every lane, so the
+// compiler can wait for just the older slot's loads. The last bonds (fewer
+// than two slots) go one at a time. The top-down pass over the sites runs
+// ahead of the bonds only as far as the next bond's lower site, with the loop
+// bounds read as wave-uniform values. The partner indices, their order and
+// every accumulation are those of cr_bonds.
+template <typename L, typename V>
+__device__ __forceinline__ L cr_bonds_pairs(uint32_t t, int n_up, const BondTable& B, Binom C, uint32_t* ylds,
+                                            V& v) {
+    L n = 0;
+    uint32_t rem = t, Es = 0, Fs = 0, X = 0;
+    int A = n_up;
+    bool one = false;
+    int p = B.n_sites - 1;  // the next site of the top-down pass
+    // runs the pass over the sites down to `lo`; X and `one` are then those of lo
+    auto advance = [&](int lo) {
+        for (; p >= lo; --p) {
+            const uint32_t cm = C(p, A - 1), c0 = C(p, A), cp = C(p, A + 1);
+            one = (A > 0) && (rem >= c0);
+            uint32_t Y;
+            if (one) {
+                X = Es - c0;
+                Y = 0u - cp - Fs;
+                Es += cm - c0;
+                Fs += cp - c0;
+                rem -= c0;
+                A -= 1;
+                n |= L(1) << p;
+            } else {
+                X = cp + Fs;
+                Y = c0 - Es;
+            }
+            ylds[p * 64] = Y;
+        }
+    };
+    constexpr int G = V::kSiteGroup;
+    const int nb = B.n_bonds;
+    // partner index and flip flag of bond b
+    auto prepare = [&](int b, uint32_t& idx, bool& anti) {
+        const int lo = __builtin_amdgcn_readfirstlane(int(B.lo(b)));
+        advance(lo);
+        const uint32_t hb = B.hi(b);
+        anti = uint32_t((n >> hb) & 1) != uint32_t(one);
+        idx = t;
+        if (anti) idx = t + X + ylds[hb * 64];
+    };
+    v.clear_slots();
+    int b = 0;
+    for (; b + 2 * G <= nb; b += 2 * G) {
+        uint32_t idx[G];
+        bool anti[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) prepare(b + g, idx[g], anti[g]);
+        v.load_slot_a(b, idx, anti);
+        v.add_slot_b();
+#pragma unroll
+        for (int g = 0; g < G; ++g) prepare(b + G + g, idx[g], anti[g]);
+        v.load_slot_b(b + G, idx, anti);
+        v.add_slot_a();
+    }
+    v.add_slot_b();
+    // the remaining bonds (fewer than 2G) one at a time
+    for (; b < nb; ++b) {
+        uint32_t idx;
+        bool anti;
+        prepare(b, idx, anti);
+        if (anti) v.flip(b, idx);
+        else v.par(b);
+    }
+    advance(0);
     return n;
 }
 
 // Visits one row t of the sector: finds its label n_t and, for every bond,
 // either reports a parallel pair or the sector index of the flipped partner
-// n_t ^ (2^i + 2^j) (Eq. 12 at s = 1/2). CLT mode reads n_t from the stored
-// basis; CR mode reconstructs it by unranking in the same pass that ranks the
-// partners.
-template <typename L, int MODE, typename V>
+// n_t ^ (2^i + 2^j) (Eq. 12 at s = 1/2). The stored-map modes (CLT, FULL,
+// LIN) read n_t from the stored basis; CR mode reconstructs it by unranking
+// in the same pass that ranks the partners.
+template <typename L, int MODE, typename V, typename Map>
 __device__ __forceinline__ L visit_row(uint32_t t, int n_up, const BondTable& B, Binom C,
-                                       const uint32_t* __restrict__ basis,
-                                       const CltEntry* __restrict__ clt, uint32_t* ylds, V& v) {
-    if constexpr (MODE == kModeClt) {
+                                       const uint32_t* __restrict__ basis, const Map& map, uint32_t* ylds, V& v) {
+    if constexpr (MODE != kModeCr) {
         const uint32_t n = *gptr(basis + t);
-        clt_bonds(n, B, clt, v);
+        table_bonds(n, B, map, v);
         return L(n);
     } else {
-        return cr_bonds<L, false>(t, L(0), n_up, B, C, ylds, v);
+        if constexpr (V::kPairs) return cr_bonds_pairs<L>(t, n_up, B, C, ylds, v);
+        else return cr_bonds<L, false>(t, L(0), n_up, B, C, ylds, v);
     }
 }
 

@@ -87,8 +87,8 @@ std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtyp
 }
 
 std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype,
-                                               std::initializer_list<const void*> ptrs) {
-    return column_chunks_v(nvec, ld, dtype, std::vector<const void*>(ptrs));
+                                               std::initializer_list<const void*> ptrs, int max_width) {
+    return column_chunks_v(nvec, ld, dtype, std::vector<const void*>(ptrs), max_width);
 }
 
 std::vector<std::pair<int, int>> job_chunks(const LanczosJob& job, int max_width) {
@@ -139,6 +139,7 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
     job.dtype = dtype;
     job.mode = devs[0].mode;
     job.n_sites = devs[0].n_sites;
+    job.two_s = devs[0].two_s > 1 ? devs[0].two_s : 1;
     job.dev_secs = dev_secs;
     job.bonds.clear();
     job.dev_bonds.clear();
@@ -178,7 +179,7 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
     }
     job.grid = int(block);
     job.lds = lds;
-    job.chunks = job_chunks(job, 32);
+    job.chunks = job_chunks(job, max_launch_width(job.two_s));
 }
 
 // Start vectors of samples r0 .. r0 + R - 1 in every sector of the job.

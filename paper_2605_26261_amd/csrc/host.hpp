@@ -24,6 +24,7 @@ struct ftlm_graph {
 
 struct ftlm_sector {
     int n_sites = 0, n_up = 0, mode = 0;
+    int two_s = 1;          // 2s of the local spin; n_up is the digit sum A when two_s > 1
     uint64_t dim = 0;
     void* table = nullptr;
     size_t bytes = 0;
@@ -111,7 +112,10 @@ struct HvTimer {
 
 std::vector<std::pair<int, int>> column_chunks_v(int nvec, uint64_t ld, int dtype, const std::vector<const void*>& ptrs,
                                                  int max_width = 32);
-std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype, std::initializer_list<const void*> ptrs);
+std::vector<std::pair<int, int>> column_chunks(int nvec, uint64_t ld, int dtype, std::initializer_list<const void*> ptrs,
+                                               int max_width = 32);
+// Widest launch of the H.x kernels of a sector: 8 columns for general spin.
+inline int max_launch_width(int two_s) { return two_s > 1 ? 8 : 32; }
 int check_dtype(int dtype);
 
 // Byte offsets of one sector's Lanczos state inside a workspace or arena.
@@ -128,7 +132,7 @@ P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(b
 // multi-sector Lanczos kernels. Host copies stay alive until the stream work
 // that reads them has been synchronized.
 struct LanczosJob {
-    int nsec = 0, R = 0, dtype = 0, mode = 0, n_sites = 0, grid = 0;
+    int nsec = 0, R = 0, dtype = 0, mode = 0, n_sites = 0, grid = 0, two_s = 1;
     size_t lds = 0;
     std::vector<SecWork> secs;           // host copies of the descriptors
     std::vector<uint64_t> keys;          // [nsec][R] stream keys of the run
@@ -138,6 +142,7 @@ struct LanczosJob {
     std::vector<BondTable*> dev_bonds;   // where each copy goes
     std::vector<std::pair<int, int>> chunks;
     int max_steps = 0;                   // largest m_eff over the sectors
+    uint32_t* queue = nullptr;           // work-queue counters of the persistent H.x (kQueueBytes)
 
     LanczosLaunch launch() const {
         LanczosLaunch a{};
@@ -149,6 +154,8 @@ struct LanczosJob {
         a.eps = dtype == FTLM_F32 ? 1e-6 : 1e-12;
         a.mode = mode;
         a.n_sites = n_sites;
+        a.two_s = two_s;
+        a.queue = queue;
         return a;
     }
 };

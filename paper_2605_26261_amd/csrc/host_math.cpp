@@ -215,7 +215,7 @@ int thermo(int n_sites, int n_sectors, const SectorSamples* sec, int nT, const d
         for (int s = 0; s < n_sectors; ++s) {
             const SectorSamples& q = sec[s];
             const double pref = q.mult * double(q.dim) / double(q.R);
-            const double mz = double(q.n_up) - 0.5 * double(n_sites);
+            const double mz = double(q.n_up) - 0.5 * double(n_sites) * double(q.two_s);  // M = A - N s
             double zs = 0.0, a1 = 0.0, a2 = 0.0;
             for (int r = 0; r < q.R; ++r) {
                 const double* th = q.theta + size_t(r) * size_t(q.stride);

@@ -6,7 +6,8 @@
 namespace ftlm {
 
 struct SectorSamples {
-    int n_up;
+    int n_up;     // digit sum A of the sector (the up-spin count at s = 1/2)
+    int two_s;    // 2s of the local spin
     int R;
     int stride;
     uint64_t dim;

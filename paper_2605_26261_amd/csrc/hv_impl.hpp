@@ -93,71 +93,55 @@ struct GatherVisitor {
     // (Lanczos step at N = 30): 8 at one column (9.0 -> 8.3 ms against 4),
     // 6 at 8 columns, 3 at 12, 2 from 16 up, 4 elsewhere.
     static constexpr int kGroup = VB == 1 ? 8 : VB == 8 ? 6 : VB == 12 ? 3 : VB >= 16 ? 2 : 4;
-    // CR: bonds of one lower site in groups of kSiteGroup, two groups deep
-    // (issue / finish below) for blocks of up to 20 columns; wider blocks take
-    // one bond at a time (flip / par).
-    static constexpr bool kPipe = VB <= 20;
+    // CR: the bonds in slots of kSiteGroup, two slots in flight (cr_bonds_pairs)
+    // for blocks of up to 20 columns; wider blocks take one bond at a time
+    // (flip / par).
+    static constexpr bool kPairs = VB <= 20;
     static constexpr int kSiteGroup = VB >= 10 ? 1 : 2;
-    // Two group buffers that take turns: one is loading while the other, issued
-    // before it, is accumulated. Rows are zero in lanes whose bond is parallel
-    // (those lanes load nothing); `phase` (wave-uniform) names the buffer the
-    // next group loads into. The turns are separate code paths, so a buffer's
-    // registers are never read before they are accumulated.
-    T bufa[kSiteGroup][VB], bufb[kSiteGroup][VB];
-    T coefa[kSiteGroup], coefb[kSiteGroup];
-    int cnta = 0, cntb = 0;
-    bool phase = false;
-    __device__ __forceinline__ void load_group(T (&buf)[kSiteGroup][VB], T (&coef)[kSiteGroup], int b0,
-                                               const uint32_t (&idx)[kSiteGroup], const bool (&flips)[kSiteGroup],
-                                               int count) {
+    // The two slots: rows of x and their weights (J_b / 2 for a flip, else 0).
+    // Every lane loads, so the loads are not under a branch and the compiler
+    // can wait for exactly the older slot: a lane whose bond is parallel
+    // loads row 0 (one cache line shared by all such lanes) under weight zero.
+    T slot_a[kSiteGroup][VB], slot_b[kSiteGroup][VB];
+    T w_a[kSiteGroup], w_b[kSiteGroup];
+    __device__ __forceinline__ void clear_slots() {
+#pragma unroll
+        for (int g = 0; g < kSiteGroup; ++g) {
+            w_a[g] = w_b[g] = T(0);
+#pragma unroll
+            for (int i = 0; i < VB; ++i) slot_a[g][i] = slot_b[g][i] = T(0);
+        }
+    }
+    // A full slot of kSiteGroup bonds b0, b0 + 1, ...
+    __device__ __forceinline__ void load_slot(T (&slot)[kSiteGroup][VB], T (&w)[kSiteGroup], int b0,
+                                              const uint32_t (&idx)[kSiteGroup], const bool (&flips)[kSiteGroup]) {
+#pragma unroll
+        for (int g = 0; g < kSiteGroup; ++g) {
+            const uint32_t c = idx[g] < last ? idx[g] : last;
+            const uint32_t i = flips[g] ? c : 0u;
+            load_row<T, VB>(x + uint64_t(i) * ld + col0, slot[g]);
+            const T cb = bond_coef<T>(B, b0 + g);
+            w[g] = flips[g] ? cb : T(0);
+        }
+    }
+    __device__ __forceinline__ void add_slot(const T (&slot)[kSiteGroup][VB], const T (&w)[kSiteGroup]) {
 #pragma unroll
         for (int g = 0; g < kSiteGroup; ++g) {
 #pragma unroll
-            for (int i = 0; i < VB; ++i) buf[g][i] = T(0);
-            coef[g] = T(0);
-            if (g < count) {
-                if (flips[g]) {
-                    const uint32_t i = idx[g] < last ? idx[g] : last;
-                    load_row<T, VB>(x + uint64_t(i) * ld + col0, buf[g]);
-                }
-                const T cb = bond_coef<T>(B, b0 + g);
-                coef[g] = flips[g] ? cb : T(0);
-            }
+            for (int i = 0; i < VB; ++i) acc[i] += w[g] * slot[g][i];
+            anti += w[g];
         }
     }
-    __device__ __forceinline__ void add_group(const T (&buf)[kSiteGroup][VB], const T (&coef)[kSiteGroup],
-                                              int count) {
-#pragma unroll
-        for (int g = 0; g < kSiteGroup; ++g) {
-            if (g < count) {
-#pragma unroll
-                for (int i = 0; i < VB; ++i) acc[i] += coef[g] * buf[g][i];
-                anti += coef[g];
-            }
-        }
+    __device__ __forceinline__ void load_slot_a(int b0, const uint32_t (&idx)[kSiteGroup],
+                                                const bool (&flips)[kSiteGroup]) {
+        load_slot(slot_a, w_a, b0, idx, flips);
     }
-    // Loads a group, then accumulates the group issued before it (bond order).
-    __device__ __forceinline__ void issue(int b0, const uint32_t (&idx)[kSiteGroup],
-                                          const bool (&flips)[kSiteGroup], int count) {
-        if (!phase) {
-            load_group(bufa, coefa, b0, idx, flips, count);
-            add_group(bufb, coefb, cntb);
-            cnta = count;
-            cntb = 0;
-        } else {
-            load_group(bufb, coefb, b0, idx, flips, count);
-            add_group(bufa, coefa, cnta);
-            cntb = count;
-            cnta = 0;
-        }
-        phase = !phase;
+    __device__ __forceinline__ void load_slot_b(int b0, const uint32_t (&idx)[kSiteGroup],
+                                                const bool (&flips)[kSiteGroup]) {
+        load_slot(slot_b, w_b, b0, idx, flips);
     }
-    // Accumulates the last group issued.
-    __device__ __forceinline__ void finish() {
-        if (phase) add_group(bufa, coefa, cnta);
-        else add_group(bufb, coefb, cntb);
-        cnta = cntb = 0;
-    }
+    __device__ __forceinline__ void add_slot_a() { add_slot(slot_a, w_a); }
+    __device__ __forceinline__ void add_slot_b() { add_slot(slot_b, w_b); }
     __device__ __forceinline__ void group(int b0, const uint32_t (&idx)[kGroup], const bool (&flips)[kGroup]) {
         T v[kGroup][VB];
 #pragma unroll
@@ -225,7 +209,7 @@ __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, 
             for (int c = 0; c < VB; ++c) acc[c] = T(0);
             T anti = T(0);
             GatherVisitor<T, VB> vis{x, ld, col0, S.dim - 1, B, acc, anti};
-            visit_row<L, MODE>(t, S.n_up, B, C, S.basis, S.clt, lds.ylds, vis);
+            visit_row<L, MODE>(t, S.n_up, B, C, S.basis, table_map<MODE>(S), lds.ylds, vis);
             load_row<T, VB>(x + uint64_t(t) * ld + col0, xt);
             const T diag = jsum4 - anti;
 #pragma unroll
@@ -321,31 +305,55 @@ __device__ __forceinline__ void alpha_tail(const SecWork& sw, const LanczosLaunc
 // and the FP64 partials of <u_k, w>; the last block of each sector sums the
 // partials in block order into alpha_k (and the update coefficient). A sector
 // whose chains have all stopped is skipped.
+//
+// With a work queue (a.queue) the grid is persistent, sized to the resident
+// workgroups: each workgroup takes (sector, block) items from its XCD's
+// counter and runs them one after the other, largest sectors first. An item
+// is exactly the work of one block of the one-block-per-item grid (same
+// tiles, same partial slot), so the reduction order, and every result, is
+// the same in both forms.
 template <typename L, int MODE, typename T, int VB>
 __global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(LanczosLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int flag;
-    uint32_t local = 0;
-    const SecWork* secs = a.secs;
-    const int s = sector_of_block(secs, a.nsec, blockIdx.x, &local);
-    if (s < 0) return;
-    const SecWork& sw = secs[s];
-    if (sw.state[1] == 0) return;
-    const int step = sw.state[0];
-    const SectorDev S = sw.S;
+    __shared__ uint32_t next;
     __shared__ BondTable B;
     __shared__ T ab[2 * VB];
-    stage_bonds(B, sw.bonds);
-    stage_epilogue<T, VB>(ab, sw.chains + a.col0);
-    const HvLds lds = hv_lds_setup<MODE>(smem, S);
-    double* wsum = lds.red;
-    for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
-    __syncthreads();
-    const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
-    T* y = static_cast<T*>(sw.u[step & 1]);
-    hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, ab, step == 1,
-                                          wsum);
-    alpha_tail<VB>(sw, a, wsum, lds.red, local, &flag);
+    const SecWork* secs = a.secs;
+    const uint32_t xcd = blockIdx.x & 7u;
+    bool first_item = true;
+    for (;;) {
+        uint32_t local = 0;
+        int s;
+        if (a.queue) {
+            if (threadIdx.x == 0) next = atomicAdd(a.queue + xcd, 1u);
+            __syncthreads();
+            s = queue_item(secs, a.nsec, xcd, next, &local);
+            __syncthreads();  // every thread has read `next`
+        } else {
+            if (!first_item) break;
+            s = sector_of_block(secs, a.nsec, blockIdx.x, &local);
+        }
+        first_item = false;
+        if (s < 0) break;
+        const SecWork& sw = secs[s];
+        if (sw.state[1] == 0) continue;
+        const int step = sw.state[0];
+        const SectorDev S = sw.S;
+        stage_bonds(B, sw.bonds);
+        stage_epilogue<T, VB>(ab, sw.chains + a.col0);
+        const HvLds lds = hv_lds_setup<MODE>(smem, S);
+        double* wsum = lds.red;
+        for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
+        __syncthreads();
+        const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
+        T* y = static_cast<T*>(sw.u[step & 1]);
+        hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, ab, step == 1,
+                                              wsum);
+        alpha_tail<VB>(sw, a, wsum, lds.red, local, &flag);
+        __syncthreads();  // LDS (bonds, scalars, tables) is restaged by the next item
+    }
+    if (a.queue) queue_exit(a.queue, gridDim.x);
 }
 
 // Dynamic LDS of the plain H.x at 20 and more FP32 columns: enough that two
@@ -370,6 +378,11 @@ hipError_t launch_hv_one(const SectorDev& s, const BondTable& B, const HvLaunch&
     return hipGetLastError();
 }
 
+// Grid of a persistent launch: the resident workgroups of the kernel at this
+// LDS size (a multiple of 8, so every XCD gets the same number), capped at
+// the number of work items.
+hipError_t persistent_grid(const void* kern, size_t lds, int items, int* grid);
+
 template <typename L, int MODE, typename T, int VB>
 hipError_t launch_lanczos_one(const LanczosLaunch& a, size_t lds, hipStream_t st) {
     auto kern = hv_lanczos_kernel<L, MODE, T, VB>;
@@ -378,7 +391,12 @@ hipError_t launch_lanczos_one(const LanczosLaunch& a, size_t lds, hipStream_t st
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(unsigned(a.grid)), dim3(kBlock), lds, st, a);
+    int grid = a.grid;
+    if (a.queue) {
+        hipError_t e = persistent_grid(reinterpret_cast<const void*>(kern), lds, a.grid, &grid);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kBlock), lds, st, a);
     return hipGetLastError();
 }
 
@@ -411,6 +429,8 @@ hipError_t with_vb(int vb, F&& f) {
 template <typename F>
 hipError_t with_mode(int mode, int n_sites, F&& f) {
     if (mode == kModeClt) return f(uint32_t{}, std::integral_constant<int, kModeClt>{});
+    if (mode == kModeFull) return f(uint32_t{}, std::integral_constant<int, kModeFull>{});
+    if (mode == kModeLin) return f(uint32_t{}, std::integral_constant<int, kModeLin>{});
     if (n_sites > 32) return f(uint64_t{}, std::integral_constant<int, kModeCr>{});
     return f(uint32_t{}, std::integral_constant<int, kModeCr>{});
 }

@@ -46,17 +46,36 @@ __device__ __forceinline__ void chain_set_hv(Chain* ch) {
     ch->hv_b_f = float(ch->hv_b_d);
 }
 
-// A sector as the kernels see it.
+// A sector as the kernels see it. Spin-1/2 sectors (two_s = 1) hold the
+// binomial table; for a local spin s = two_s / 2 > 1/2, n_up is the sector's
+// digit sum A (Eq. 17), `binom` holds the cumulative dimension table of
+// Eq. (16) as [N][bw][two_s + 1] (spin.hpp), and labels are base-(two_s + 1)
+// integers below n_labels (Eq. 11).
 struct SectorDev {
     int n_sites;
     int n_up;
     int mode;
-    int bw;                  // binomial table row width
+    int bw;                  // binomial table row width (A slots of the D_c table)
     uint32_t dim;
-    const uint32_t* binom;   // [N][bw]
+    const uint32_t* binom;   // [N][bw] (spin 1/2) or [N][bw][two_s + 1]
     const uint32_t* basis;   // [D] (CLT mode)
-    const CltEntry* clt;     // [2^N / 32] (CLT mode)
+    const CltEntry* clt;     // [n_labels / 32] (CLT mode)
+    int two_s;               // 2s: 1 for spin 1/2
+    uint64_t n_labels;       // d^N, d = two_s + 1
+    const uint32_t* full;    // [2^N] sector index per label (FULL mode)
+    const uint32_t* lin_hi;  // [2^(N - lin_lo)] (LIN mode)
+    const uint32_t* lin_lo;  // [2^lin_lo] (LIN mode)
+    int lin_lo_bits;
 };
+
+// The stored partner-index map of a sector (CR keeps none; it gets a CLT
+// map that is never read).
+template <int MODE>
+__device__ __forceinline__ auto table_map(const SectorDev& S) {
+    if constexpr (MODE == kModeFull) return TableMap<kModeFull>{S.full};
+    else if constexpr (MODE == kModeLin) return TableMap<kModeLin>{S.lin_hi, S.lin_lo, S.lin_lo_bits};
+    else return TableMap<kModeClt>{S.clt};
+}
 
 enum Epilogue { kEpiPlain = 0, kEpiLanczos = 1 };
 
@@ -112,9 +131,29 @@ struct LanczosLaunch {
     int dist;            // start-vector distribution
     int mode;            // index mode shared by the sectors (host dispatch)
     int n_sites;         // N shared by the sectors (host dispatch)
+    int two_s;           // local spin 2s shared by the sectors (host dispatch)
+    // Work queue of the persistent H.x launch (kQueueWords counters, zero
+    // between launches), or null for a grid of one block per work item.
+    uint32_t* queue;
 };
 
+// The persistent Lanczos H.x takes its work items from eight counters, one
+// per XCD, and counts its exiting blocks in a ninth; the last block to exit
+// zeroes all nine for the next launch on the stream.
+constexpr int kQueueWords = 9;
+constexpr size_t kQueueBytes = 256;
+
 hipError_t launch_hv(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st);
+// General-spin sectors (two_s > 1; hv_spin.hip).
+hipError_t launch_hv_spin(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st);
+hipError_t launch_hv_lanczos_spin(const LanczosLaunch& a, size_t lds, hipStream_t st);
+hipError_t launch_build_basis_spin(const SectorDev& s, hipStream_t st);
+hipError_t launch_build_clt_spin(const SectorDev& s, hipStream_t st);
+hipError_t launch_rank_spin(const SectorDev& s, const uint64_t* labels, uint64_t* idx, uint64_t n, hipStream_t st);
+hipError_t launch_unrank_spin(const SectorDev& s, const uint64_t* idx, uint64_t* labels, uint64_t n,
+                              hipStream_t st);
+hipError_t launch_neighbors_spin(const SectorDev& s, const BondTable& B, uint64_t t0, uint64_t count,
+                                 uint64_t* out, hipStream_t st);
 hipError_t launch_hv_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st);
 hipError_t launch_start(const LanczosLaunch& a, hipStream_t st);
 hipError_t launch_update(const LanczosLaunch& a, hipStream_t st);
@@ -123,6 +162,8 @@ hipError_t launch_chain_init(const LanczosLaunch& a, hipStream_t st);
 // Sector table builders and index kernels (sector.hip).
 hipError_t launch_build_basis(const SectorDev& s, hipStream_t st);
 hipError_t launch_build_clt(const SectorDev& s, hipStream_t st);
+hipError_t launch_build_full(const SectorDev& s, hipStream_t st);
+hipError_t launch_build_lin(const SectorDev& s, hipStream_t st);
 hipError_t launch_rank(const SectorDev& s, const uint64_t* labels, uint64_t* idx, uint64_t n,
                        hipStream_t st);
 hipError_t launch_unrank(const SectorDev& s, const uint64_t* idx, uint64_t* labels, uint64_t n,
@@ -139,7 +180,18 @@ __host__ __device__ inline size_t hv_binom_lds_bytes(int n_sites, int bw, int mo
 __host__ __device__ inline size_t hv_slab_lds_bytes(int n_sites, int mode) {
     return mode == kModeCr ? size_t(kWaves) * size_t(n_sites) * 64 * 4 : 0;
 }
+// General spin: the FP64 scratch, the ladder factors (FP64 and FP32, eight
+// each), then (every mode) the cumulative dimension table or (CLT) the powers
+// d^p, and (CR) two [site][lane] slabs per wave.
+__host__ __device__ inline size_t hv_spin_table_lds_bytes(const SectorDev& s) {
+    const size_t t = s.mode == kModeCr ? size_t(s.n_sites) * size_t(s.bw) * size_t(s.two_s + 1) : size_t(s.n_sites);
+    return (t * 4 + 15) & ~size_t(15);
+}
+__host__ __device__ inline size_t hv_spin_lds_bytes(const SectorDev& s) {
+    return hv_red_bytes() + 8 * 8 + 8 * 4 + hv_spin_table_lds_bytes(s) + 2 * hv_slab_lds_bytes(s.n_sites, s.mode);
+}
 __host__ __device__ inline size_t hv_lds_bytes(const SectorDev& s) {
+    if (s.two_s > 1) return hv_spin_lds_bytes(s);
     return hv_red_bytes() + hv_binom_lds_bytes(s.n_sites, s.bw, s.mode) + hv_slab_lds_bytes(s.n_sites, s.mode);
 }
 
@@ -153,6 +205,36 @@ __host__ __device__ inline uint32_t rows_grid(uint32_t nrows) {
     const uint32_t cap = 2048;
     const uint32_t g = tiles < cap ? tiles : cap;
     return (g + 7) & ~7u;
+}
+
+// Work item k of XCD x in a persistent launch: the sectors' blocks whose
+// index inside the sector is x mod 8, sector by sector in launch order (a
+// block index keeps its XCD, so the tile order of for_each_tile still gives
+// each XCD its contiguous share). Returns the sector and *local, or -1 when
+// the XCD's items are exhausted.
+__device__ __forceinline__ int queue_item(const SecWork* secs, int nsec, uint32_t xcd, uint32_t k,
+                                          uint32_t* local) {
+    for (int s = 0; s < nsec; ++s) {
+        const uint32_t G = secs[s].G;
+        const uint32_t cnt = G > xcd ? (G - xcd + 7u) / 8u : 0u;
+        if (k < cnt) {
+            *local = xcd + 8u * k;
+            return s;
+        }
+        k -= cnt;
+    }
+    return -1;
+}
+
+// Called by every block of a persistent launch after its last item: the last
+// block to get here zeroes the counters (every block has stopped taking items).
+__device__ __forceinline__ void queue_exit(uint32_t* q, uint32_t grid) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(q + 8, 1u);
+        if (done == grid - 1u)
+            for (int i = 0; i < kQueueWords; ++i) atomicExch(q + i, 0u);
+    }
 }
 
 // The sector owning block `b` of a multi-sector launch, by a wave-uniform

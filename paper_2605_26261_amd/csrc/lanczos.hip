@@ -5,6 +5,10 @@
 // every sector of a plan; each sector owns a contiguous range of blocks.
 #include <math.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "hv_impl.hpp"
 
 namespace ftlm {
@@ -12,7 +16,33 @@ namespace ftlm {
 template <typename T>
 hipError_t launch_lanczos_typed(int, int, const LanczosLaunch&, size_t, hipStream_t);
 
+hipError_t persistent_grid(const void* kern, size_t lds, int items, int* grid) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, size_t>, int> cache;  // per kernel and LDS size
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find({kern, lds});
+        if (it != cache.end()) {
+            per_cu = it->second;
+        } else {
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
+            if (e != hipSuccess) return e;
+            cache[{kern, lds}] = per_cu;
+        }
+    }
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int resident = ((std::max(1, per_cu) * cus + 7) / 8) * 8;
+    const int cap = ((items + 7) / 8) * 8;
+    *grid = std::max(8, std::min(resident, cap));
+    return hipSuccess;
+}
+
 hipError_t launch_hv_lanczos(const LanczosLaunch& a, size_t lds, hipStream_t st) {
+    if (a.two_s > 1) return launch_hv_lanczos_spin(a, lds, st);
     return a.dtype == 0 ? launch_lanczos_typed<float>(a.mode, a.n_sites, a, lds, st)
                         : launch_lanczos_typed<double>(a.mode, a.n_sites, a, lds, st);
 }
@@ -298,6 +328,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
 // Zeroes every sector's chain states and ticket and sets its step counter to
 // 1 with no active chains (one block per sector).
 __global__ void chain_init_kernel(LanczosLaunch a) {
+    if (blockIdx.x == 0 && a.queue && threadIdx.x < unsigned(kQueueWords)) a.queue[threadIdx.x] = 0u;
     if (int(blockIdx.x) >= a.nsec) return;
     const SecWork& sw = a.secs[blockIdx.x];
     for (int i = threadIdx.x; i < int(a.ld); i += blockDim.x) {

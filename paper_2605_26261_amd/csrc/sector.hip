@@ -8,6 +8,7 @@ template <typename T>
 hipError_t launch_hv_typed(const SectorDev&, const BondTable&, const HvLaunch&, hipStream_t);
 
 hipError_t launch_hv(const SectorDev& s, const BondTable& B, const HvLaunch& h, hipStream_t st) {
+    if (s.two_s > 1) return launch_hv_spin(s, B, h, st);
     return h.dtype == 0 ? launch_hv_typed<float>(s, B, h, st) : launch_hv_typed<double>(s, B, h, st);
 }
 
@@ -72,6 +73,37 @@ __global__ __launch_bounds__(kThreads) void build_clt_kernel(SectorDev S, CltEnt
     }
 }
 
+// The full lookup table (Sec. 2): for every label of [0, 2^N) its sector
+// index (the count of sector labels below it) or kNone32.
+__global__ __launch_bounds__(kThreads) void build_full_kernel(SectorDev S, uint32_t* full) {
+    extern __shared__ uint32_t lds[];
+    stage_binomials(lds, S.binom, S.n_sites * S.bw);
+    const Binom C{lds, S.bw};
+    const uint64_t limit = uint64_t(1) << S.n_sites;
+    for (uint64_t x = global_id(); x < limit; x += global_stride())
+        full[x] = __popcll(x) == S.n_up ? count_below<uint64_t>(x, S.n_sites, S.n_up, C) : kNone32;
+}
+
+// Lin's two tables over the split label = (high part h, low part l of L
+// bits): hi[h] = the number of sector labels below h * 2^L (the ones whose
+// high part is smaller), lo[l] = the rank of l among the L-bit strings with
+// popcount(l) up spins (Alg. 1 over the L low positions). A sector label
+// (h, l) then has index hi[h] + lo[l], ascending order preserved. Low parts
+// with more up spins than the sector holds never occur; they get 0.
+__global__ __launch_bounds__(kThreads) void build_lin_kernel(SectorDev S, uint32_t* hi, uint32_t* lo) {
+    extern __shared__ uint32_t lds[];
+    stage_binomials(lds, S.binom, S.n_sites * S.bw);
+    const Binom C{lds, S.bw};
+    const int L = S.lin_lo_bits;
+    const uint64_t nhi = uint64_t(1) << (S.n_sites - L), nlo = uint64_t(1) << L;
+    for (uint64_t h = global_id(); h < nhi; h += global_stride())
+        hi[h] = count_below<uint64_t>(h << L, S.n_sites, S.n_up, C);
+    for (uint64_t l = global_id(); l < nlo; l += global_stride()) {
+        const int k = __popcll(l);
+        lo[l] = k <= S.n_up ? cr_rank<uint64_t>(l, L, k, C) : 0u;
+    }
+}
+
 template <typename L>
 __global__ __launch_bounds__(kThreads) void rank_kernel(SectorDev S, const uint64_t* labels, uint64_t* idx,
                                                         uint64_t n) {
@@ -86,8 +118,16 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(SectorDev S, const uint6
             if (S.mode == kModeClt) {
                 const uint32_t r = clt_lookup(S.clt, uint32_t(x));
                 if (r != kNone32) out = r;
+            } else if (S.mode == kModeFull) {
+                const uint32_t r = S.full[x];
+                if (r != kNone32) out = r;
             } else if (__popcll(x) == S.n_up) {
-                out = cr_rank<L>(L(x), S.n_sites, S.n_up, C);
+                if (S.mode == kModeLin) {
+                    const TableMap<kModeLin> m{S.lin_hi, S.lin_lo, S.lin_lo_bits};
+                    out = m.index(m.fetch(uint32_t(x)), uint32_t(x));
+                } else {
+                    out = cr_rank<L>(L(x), S.n_sites, S.n_up, C);
+                }
             }
         }
         idx[i] = out;
@@ -104,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void unrank_kernel(SectorDev S, const uin
         const uint64_t t = idx[i];
         uint64_t out = ~uint64_t(0);
         if (t < S.dim) {
-            if (S.mode == kModeClt) out = S.basis[t];
+            if (S.mode != kModeCr) out = S.basis[t];
             else out = uint64_t(cr_unrank<L>(uint32_t(t), S.n_sites, S.n_up, C));
         }
         labels[i] = out;
@@ -117,7 +157,7 @@ struct NeighborVisitor {
     uint64_t* out;
     const BondTable& B;
     static constexpr int kGroup = 2;
-    static constexpr bool kPipe = false;
+    static constexpr bool kPairs = false;
     static constexpr int kSiteGroup = 2;
     __device__ __forceinline__ void flip(int b, uint32_t idx) { out[B.orig(b)] = idx; }
     __device__ __forceinline__ void site_group(int b0, const uint32_t (&idx)[kSiteGroup],
@@ -145,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void neighbors_kernel(SectorDev S, BondTabl
     uint32_t* ylds = slabs + wave * S.n_sites * 64 + lane;
     for (uint64_t r = global_id(); r < count; r += global_stride()) {
         NeighborVisitor v{out + r * uint64_t(B.n_bonds), B};
-        visit_row<L, MODE>(uint32_t(t0 + r), S.n_up, B, C, S.basis, S.clt, ylds, v);
+        visit_row<L, MODE>(uint32_t(t0 + r), S.n_up, B, C, S.basis, table_map<MODE>(S), ylds, v);
     }
 }
 
@@ -163,6 +203,22 @@ hipError_t launch_build_clt(const SectorDev& s, hipStream_t st) {
     const uint64_t nb = clt_blocks(s.n_sites);
     hipLaunchKernelGGL(build_clt_kernel, dim3(blocks_for(nb)), dim3(kThreads), lds, st, s,
                        const_cast<CltEntry*>(s.clt), nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_full(const SectorDev& s, hipStream_t st) {
+    const size_t lds = size_t(s.n_sites) * s.bw * 4;
+    hipLaunchKernelGGL(build_full_kernel, dim3(blocks_for(uint64_t(1) << s.n_sites)), dim3(kThreads), lds, st, s,
+                       const_cast<uint32_t*>(s.full));
+    return hipGetLastError();
+}
+
+hipError_t launch_build_lin(const SectorDev& s, hipStream_t st) {
+    const size_t lds = size_t(s.n_sites) * s.bw * 4;
+    const uint64_t n = uint64_t(1) << (s.n_sites - s.lin_lo_bits > s.lin_lo_bits ? s.n_sites - s.lin_lo_bits
+                                                                                  : s.lin_lo_bits);
+    hipLaunchKernelGGL(build_lin_kernel, dim3(blocks_for(n)), dim3(kThreads), lds, st, s,
+                       const_cast<uint32_t*>(s.lin_hi), const_cast<uint32_t*>(s.lin_lo));
     return hipGetLastError();
 }
 
@@ -192,6 +248,10 @@ hipError_t launch_neighbors(const SectorDev& s, const BondTable& B, uint64_t t0,
     const dim3 grid(blocks_for(count)), block(kBlock);
     if (s.mode == kModeClt)
         hipLaunchKernelGGL((neighbors_kernel<uint32_t, kModeClt>), grid, block, lds, st, s, B, t0, count, out);
+    else if (s.mode == kModeFull)
+        hipLaunchKernelGGL((neighbors_kernel<uint32_t, kModeFull>), grid, block, lds, st, s, B, t0, count, out);
+    else if (s.mode == kModeLin)
+        hipLaunchKernelGGL((neighbors_kernel<uint32_t, kModeLin>), grid, block, lds, st, s, B, t0, count, out);
     else if (s.n_sites > 32)
         hipLaunchKernelGGL((neighbors_kernel<uint64_t, kModeCr>), grid, block, lds, st, s, B, t0, count, out);
     else

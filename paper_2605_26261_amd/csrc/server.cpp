@@ -33,6 +33,13 @@ namespace {
 
 constexpr int kServerMaxActive = 256;
 constexpr int kServerDefaultActive = 16;
+
+// The arena's header: the descriptors of up to kServerMaxActive requests, then
+// the work-queue counters of the persistent H.x launches (one set serves
+// every launch: the worker's launches run one after the other on its stream
+// and each leaves the counters at zero).
+size_t server_desc_bytes() { return align256(size_t(kServerMaxActive) * sizeof(SecWork)); }
+size_t server_header_bytes() { return server_desc_bytes() + kQueueBytes; }
 constexpr int kServerMaxSteps = 64;
 constexpr int kServerDefaultSteps = 4;
 
@@ -165,6 +172,7 @@ struct ftlm_server {
     std::atomic<uint64_t> rounds{0}, peak{0};
     std::atomic<int32_t> n_active{0};
 
+    uint32_t* queue() const { return reinterpret_cast<uint32_t*>(arena + server_desc_bytes()); }
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -187,6 +195,7 @@ int ftlm_server::admit(const std::shared_ptr<Request>& r) {
     job_layout(r->job, {r->sector->dev}, {L.st}, base, r->R, r->M, opts.dtype,
                reinterpret_cast<SecWork*>(base + L.secwork), {r->graph},
                {reinterpret_cast<BondTable*>(base + L.bonds)}, {0});
+    r->job.queue = queue();
     if (int rc = job_start(r->job, r->seed, 0, r->dist, stream)) return rc;
     r->t_admit = now();
     return FTLM_OK;
@@ -265,6 +274,7 @@ int ftlm_server::round() {
         // equal R and 256-byte aligned blocks give every member the same chunks
         g.chunks = reqs[0]->job.chunks;
         g.dev_secs = desc + slot;
+        g.queue = queue();
         slot += reqs.size();
         jobs.push_back(std::move(g));
     }
@@ -290,7 +300,7 @@ int ftlm_server::round() {
 }
 
 void ftlm_server::run() {
-    const size_t desc_bytes = align256(size_t(kServerMaxActive) * sizeof(SecWork));
+    const size_t desc_bytes = server_header_bytes();
     heap.init(desc_bytes, arena_bytes);
     const size_t max_active = size_t(opts.max_active > 0 ? std::min(opts.max_active, kServerMaxActive)
                                                          : kServerDefaultActive);
@@ -376,14 +386,15 @@ int ftlm_server_request_bytes(const ftlm_request* req, int mode, int dtype, size
 int ftlm_server_create(void* arena_dev, size_t arena_bytes, const ftlm_server_opts* opts, ftlm_server** out) {
     if (!arena_dev || !opts || !out) return fail(FTLM_E_INVALID, "null argument");
     *out = nullptr;
-    if (opts->mode != FTLM_CLT && opts->mode != FTLM_CR) return fail(FTLM_E_INVALID, "mode %d", opts->mode);
+    if (opts->mode != FTLM_CLT && opts->mode != FTLM_CR && opts->mode != FTLM_FULL && opts->mode != FTLM_LIN)
+        return fail(FTLM_E_INVALID, "mode %d", opts->mode);
     if (int rc = check_dtype(opts->dtype)) return rc;
     if (opts->max_active < 0 || opts->max_active > kServerMaxActive)
         return fail(FTLM_E_RANGE, "max_active %d not in [0, %d]", opts->max_active, kServerMaxActive);
     if (opts->steps_per_round < 0 || opts->steps_per_round > kServerMaxSteps)
         return fail(FTLM_E_RANGE, "steps_per_round %d not in [0, %d]", opts->steps_per_round, kServerMaxSteps);
     if (reinterpret_cast<uintptr_t>(arena_dev) % 256 != 0) return fail(FTLM_E_INVALID, "arena not 256-byte aligned");
-    const size_t desc = align256(size_t(kServerMaxActive) * sizeof(SecWork));
+    const size_t desc = server_header_bytes();
     if (arena_bytes <= desc) return fail(FTLM_E_NOSPACE, "arena smaller than its descriptor area (%zu bytes)", desc);
     auto* s = new ftlm_server();
     s->arena = static_cast<char*>(arena_dev);
@@ -416,7 +427,7 @@ int ftlm_server_submit(ftlm_server* s, const ftlm_request* req, uint64_t* id) {
     if (int rc = check_request(req)) return rc;
     ReqLayout L;
     if (int rc = request_layout(req->n_sites, req->n_up, req->R, s->opts.mode, s->opts.dtype, L)) return rc;
-    const size_t usable = s->arena_bytes - align256(size_t(kServerMaxActive) * sizeof(SecWork));
+    const size_t usable = s->arena_bytes - server_header_bytes();
     if (L.total > usable)
         return fail(FTLM_E_REJECTED, "request needs %zu bytes, the arena holds %zu", L.total, usable);
     auto r = std::make_shared<Request>();

@@ -18,29 +18,31 @@ def log_temperatures(n=200, t_min=0.05, t_max=10.0):
     return t_min * (t_max / t_min) ** (k / (n - 1))
 
 
-def records_from_coefficients(n_sites, n_up, dim, alpha, beta, steps):
-    """Host Ritz solves of R chains -> a thermo record of the sector."""
+def records_from_coefficients(n_sites, n_up, dim, alpha, beta, steps, two_s=1):
+    """Host Ritz solves of R chains -> a thermo record of the sector (n_up:
+    the digit sum A when two_s > 1)."""
     theta, weight = ftlm.ritz_batch(alpha, beta, steps)
-    return {"n_up": n_up, "dim": dim, "mult": multiplicity(n_sites, n_up), "theta": theta, "weight": weight,
-            "steps": np.asarray(steps), "alpha": alpha, "beta": beta}
+    return {"n_up": n_up, "two_s": two_s, "dim": dim, "mult": ftlm.sector_info_spin(n_sites, two_s, n_up)[1],
+            "theta": theta, "weight": weight, "steps": np.asarray(steps), "alpha": alpha, "beta": beta}
 
 
 def sector_samples(sector, graph, R, M, seed, dist, dtype, r0=0, work=None, stream=None):
     """Runs R chains in one batch; returns the thermo record of the sector."""
     alpha, beta, steps = ftlm.lanczos(sector, graph, seed, r0, R, M, dist, dtype, work=work, stream=stream)
-    return records_from_coefficients(sector.n_sites, sector.n_up, sector.dim, alpha, beta, steps)
+    return records_from_coefficients(sector.n_sites, sector.n_up, sector.dim, alpha, beta, steps,
+                                     getattr(sector, "two_s", 1))
 
 
 def run(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, temps=None, g=1.0,
-        batch=None, device="cuda"):
-    """Full FTLM over the listed sectors. Chains run in batches of `batch`
-    (default: all R at once; "auto": the autotuned width). Returns (thermo
-    dict, per-sector records)."""
+        batch=None, device="cuda", two_s=1):
+    """Full FTLM over the listed sectors (n_ups: digit sums A when two_s =
+    2s > 1). Chains run in batches of `batch` (default: all R at once;
+    "auto": the autotuned width). Returns (thermo dict, per-sector records)."""
     temps = log_temperatures() if temps is None else temps
     graph = ftlm.Graph(n_sites, bonds)
     recs = []
     for n_up in n_ups:
-        sec = ftlm.Sector(n_sites, n_up, mode, device=device)
+        sec = ftlm.Sector(n_sites, n_up, mode, device=device, two_s=two_s)
         if batch == "auto":
             b = ftlm.autotune(sec, graph, R, dtype)["batch"]
         else:
@@ -48,7 +50,7 @@ def run(n_sites, bonds, n_ups, R, M, seed, dist, dtype=ftlm.F32, mode=ftlm.CR, t
         parts = []
         for r0 in range(0, R, b):
             parts.append(sector_samples(sec, graph, min(b, R - r0), M, seed, dist, dtype, r0=r0))
-        rec = {k: parts[0][k] for k in ("n_up", "dim", "mult")}
+        rec = {k: parts[0][k] for k in ("n_up", "two_s", "dim", "mult")}
         for k in ("theta", "weight", "steps", "alpha", "beta"):
             rec[k] = np.concatenate([p[k] for p in parts])
         recs.append(rec)

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libftlm.so")
 
 OK, E_INVALID, E_RANGE, E_NOSPACE, E_DEVICE, E_AGAIN, E_REJECTED, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6, -7
-CLT, CR = 0, 1
+CLT, CR, FULL, LIN = 0, 1, 2, 3
 F32, F64 = 0, 1
 PM1, GAUSS, UNIT = 0, 1, 2
 NONE = (1 << 64) - 1
@@ -40,7 +40,7 @@ _vp, _u64, _i32, _i64, _sz, _dbl = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_i
 class SectorResult(ctypes.Structure):
     """ftlm_sector_result."""
     _fields_ = [("n_up", ctypes.c_int32), ("R", ctypes.c_int32), ("stride", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("dim", ctypes.c_uint64), ("mult", ctypes.c_double),
+                ("two_s", ctypes.c_int32), ("dim", ctypes.c_uint64), ("mult", ctypes.c_double),
                 ("theta", _vp), ("weight", _vp), ("steps", _vp)]
 
 
@@ -63,6 +63,10 @@ _sig("ftlm_sector_create", _i32, [_i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTE
 _sig("ftlm_sector_dim", _u64, [_vp])
 _sig("ftlm_sector_mode", _i32, [_vp])
 _sig("ftlm_sector_destroy", None, [_vp])
+_sig("ftlm_sector_info_spin", _i32, [_i32, _i32, _i32, ctypes.POINTER(_u64), ctypes.POINTER(_dbl)])
+_sig("ftlm_sector_table_bytes_spin", _i32, [_i32, _i32, _i32, _i32, ctypes.POINTER(_sz)])
+_sig("ftlm_sector_create_spin", _i32, [_i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)])
+_sig("ftlm_sector_two_s", _i32, [_vp])
 _sig("ftlm_rank", _i32, [_vp, _vp, _vp, _u64, _vp])
 _sig("ftlm_unrank", _i32, [_vp, _vp, _vp, _u64, _vp])
 _sig("ftlm_clt_export", _i32, [_vp, _vp, _vp, _u64, _vp])
@@ -209,17 +213,34 @@ def sector_table_bytes(n_sites, n_up, mode):
     return n.value
 
 
-class Sector:
-    """ftlm_sector with its device table buffer (owned by this object)."""
+def sector_info_spin(n_sites, two_s, a_tot):
+    """ftlm_sector_info_spin: (D, multiplicity) of the sector with digit sum
+    a_tot of N sites of spin two_s / 2."""
+    d, m = _u64(), _dbl()
+    _check(_lib.ftlm_sector_info_spin(n_sites, two_s, a_tot, ctypes.byref(d), ctypes.byref(m)))
+    return int(d.value), float(m.value)
 
-    def __init__(self, n_sites, n_up, mode, device="cuda", stream=None, table=None):
-        nbytes = sector_table_bytes(n_sites, n_up, mode)
+
+def sector_table_bytes_spin(n_sites, two_s, a_tot, mode):
+    n = _sz()
+    _check(_lib.ftlm_sector_table_bytes_spin(n_sites, two_s, a_tot, mode, ctypes.byref(n)))
+    return n.value
+
+
+class Sector:
+    """ftlm_sector with its device table buffer (owned by this object).
+    n_up is the sector's digit sum A (Eq. 17) when two_s = 2s > 1."""
+
+    def __init__(self, n_sites, n_up, mode, device="cuda", stream=None, table=None, two_s=1):
+        nbytes = sector_table_bytes_spin(n_sites, two_s, n_up, mode)
         self.table = table if table is not None else _empty_device(nbytes, device)
+        if self.table.numel() < nbytes:
+            raise ValueError(f"table holds {self.table.numel()} bytes, {nbytes} needed")
         h = _vp()
-        _check(_lib.ftlm_sector_create(n_sites, n_up, mode, _dptr(self.table), self.table.numel(),
-                                       _stream(stream), ctypes.byref(h)))
+        _check(_lib.ftlm_sector_create_spin(n_sites, two_s, n_up, mode, _dptr(self.table), self.table.numel(),
+                                            _stream(stream), ctypes.byref(h)))
         self.handle = h
-        self.n_sites, self.n_up, self.mode = n_sites, n_up, mode
+        self.n_sites, self.n_up, self.mode, self.two_s = n_sites, n_up, mode, two_s
 
     @property
     def dim(self):
@@ -260,8 +281,10 @@ def clt_export(sector, nblocks, stream=None):
 
 def neighbors(sector, graph, t0, count, out, stream=None):
     import torch
-    if out.dtype not in (torch.int64, torch.uint64) or out.numel() < count * graph.n_bonds:
-        raise ValueError("out must be an 8-byte integer tensor of at least count * n_bonds entries")
+    per_row = graph.n_bonds * (2 if getattr(sector, "two_s", 1) > 1 else 1)
+    if out.dtype not in (torch.int64, torch.uint64) or out.numel() < count * per_row:
+        raise ValueError("out must be an 8-byte integer tensor of at least count * n_bonds entries "
+                         "(2 * n_bonds for general spin)")
     _check(_lib.ftlm_neighbors(sector.handle, graph.handle, t0, count, _dptr(out), _stream(stream)))
 
 
@@ -541,7 +564,7 @@ def thermo(n_sites, sectors, temps, g=1.0):
         w = np.ascontiguousarray(s["weight"], dtype=np.float64)
         st = np.ascontiguousarray(s["steps"], dtype=np.int32)
         keep += [th, w, st]
-        recs[i] = SectorResult(s["n_up"], th.shape[0], th.shape[1], 0, s["dim"], s["mult"],
+        recs[i] = SectorResult(s["n_up"], th.shape[0], th.shape[1], int(s.get("two_s", 1)), s["dim"], s["mult"],
                                th.ctypes.data, w.ctypes.data, st.ctypes.data)
     temps = np.ascontiguousarray(temps, dtype=np.float64)
     out = {k: np.empty(len(temps)) for k in ("E", "C", "chi", "lnZ")}

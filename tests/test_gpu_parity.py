@@ -39,7 +39,7 @@ def _np_u64(t):
 SMALL = [(n, k) for n in (2, 5, 9, 12, 16) for k in range(n + 1)] + [(20, 10), (20, 7), (24, 12), (24, 23)]
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("n,n_up", SMALL)
 def test_rank_unrank_exhaustive(env, mode, n, n_up):
     torch, ftlm = env
@@ -65,7 +65,8 @@ def test_rank_unrank_exhaustive(env, mode, n, n_up):
     np.testing.assert_array_equal(_np_u64(pr), oracle.rank(n, n_up, probe))
 
 
-@pytest.mark.parametrize("mode,n,n_up", [(0, 30, 15), (1, 30, 15), (1, 34, 17), (0, 28, 16), (1, 33, 20)])
+@pytest.mark.parametrize("mode,n,n_up", [(0, 30, 15), (1, 30, 15), (1, 34, 17), (0, 28, 16), (1, 33, 20),
+                                         (2, 30, 15), (3, 30, 15), (3, 31, 9)])
 def test_rank_unrank_sampled_large(env, mode, n, n_up):
     torch, ftlm = env
     sec = ftlm.Sector(n, n_up, mode)
@@ -121,7 +122,7 @@ GRAPHS = [
 ]
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("n,bonds", GRAPHS)
 def test_neighbors_exhaustive(env, mode, n, bonds):
     torch, ftlm = env
@@ -138,7 +139,8 @@ def test_neighbors_exhaustive(env, mode, n, bonds):
 @pytest.mark.parametrize("mode,n,bonds", [
     (0, 30, graphs.icosidodecahedron()), (1, 30, graphs.icosidodecahedron()),
     (1, 30, graphs.icosidodecahedron(order="raw")), (1, 34, graphs.j1j2_ring(34, 1.0, 0.3)),
-    (0, 24, graphs.square_j1j2()), (1, 24, graphs.square_j1j2())])
+    (0, 24, graphs.square_j1j2()), (1, 24, graphs.square_j1j2()),
+    (2, 30, graphs.icosidodecahedron()), (3, 30, graphs.icosidodecahedron())])
 def test_neighbors_sampled_windows(env, mode, n, bonds):
     torch, ftlm = env
     n_up = n // 2
@@ -174,14 +176,16 @@ def test_hv_parity_multivector(env, nvec, n, bonds):
         xs = x.double().cpu().numpy()  # the values the kernel sees
         want = np.stack([oracle.hv(n, n_up, bonds, xs[:, c], b) for c in range(nvec)], axis=1)
         outs = []
-        for mode in (0, 1):
+        for mode in (0, 1, 2, 3):
             sec = ftlm.Sector(n, n_up, mode)
             y = torch.empty_like(x)
             ftlm.hv(sec, g, x, y)
             got = y.double().cpu().numpy()
             assert _rel_l2(got, want) <= tol, (mode, dtype, _rel_l2(got, want))
             outs.append(got)
-        np.testing.assert_array_equal(outs[0], outs[1])
+        # every index map visits the bonds in the same order: bitwise the same
+        for o in outs[1:]:
+            np.testing.assert_array_equal(outs[0], o)
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -219,13 +223,15 @@ def test_hv_n30_modes_bit_identical(env):
     gen = torch.Generator(device="cuda").manual_seed(9)
     x = torch.randn(math.comb(30, 15), 4, dtype=torch.float32, device="cuda", generator=gen)
     ys = []
-    for mode in (0, 1):
+    for mode in (0, 1, 2, 3):
         sec = ftlm.Sector(n, n_up, mode)
         y = torch.empty_like(x)
         ftlm.hv(sec, g, x, y)
         ys.append(y)
         del sec
-    assert torch.equal(ys[0], ys[1])
+        torch.cuda.empty_cache()
+    for y in ys[1:]:
+        assert torch.equal(ys[0], y)
 
 
 def test_hv_rows_shard(env):

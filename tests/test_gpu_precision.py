@@ -1,0 +1,116 @@
+"""The precision pattern on the GPU (Sec. 3.1-3.3): FTLM with FP32 Krylov
+vectors and FP64 reductions against the FP64 oracle with the same start
+vectors, set against the stochastic error of the method.
+
+* N = 18 J1-J2 ring, all S^z >= 0 sectors, R = 8, M = 60 (FP64 reference:
+  tests/golden/ring18_r8.json) and the 6x4 J1-J2 lattice, all 13 sectors,
+  R = 2, M = 80 (tests/golden/square4x6_r2.json): the FP32 run's |dE|, |dC|,
+  |dchi| stay within 1e-4 of the observable's scale and below 1 % of
+  sigma_emp (Eq. 22) over 10 further seeds at the same R, at every
+  temperature where the spread is not negligible.
+* Ghost diagnostic (Sec. 3.2, Eq. 25): FP32 and FP64 chains from the same
+  start vector, far past the convergence of the low end of the spectrum;
+  the clusters of both precisions carry the same weights.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from ftlm_inputs import graphs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+N_SEEDS = 10
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_26261_amd import driver, ftlm
+    return torch, ftlm, driver
+
+
+def _fp32_vs_spread(ftlm, driver, n, bonds, n_ups, R, M, seed, ref, temps):
+    """FP32 plan run with the reference's seed, and the spread over
+    N_SEEDS more seeds; returns {obs: (|dO| [T], sigma [T], O64 [T])}."""
+    g = ftlm.Graph(n, bonds)
+    plan = ftlm.Plan(g, n_ups, ftlm.CR, R, M, ftlm.F32)
+    th = ftlm.thermo(n, driver.plan_records(plan, n, seed, ftlm.PM1), temps, 1.0)
+    runs = {k: [] for k in ("E", "C", "chi")}
+    for s in range(N_SEEDS):
+        ts = ftlm.thermo(n, driver.plan_records(plan, n, 1000 + s, ftlm.PM1), temps, 1.0)
+        for k in runs:
+            runs[k].append(ts[k])
+    out = {}
+    for k in runs:
+        _, sig = ftlm.seed_spread(np.array(runs[k]))
+        o64 = np.asarray(ref[k])
+        out[k] = (np.abs(th[k] - o64), sig, o64)
+    return out
+
+
+def _check(out, label):
+    for k, (d, sig, o64) in out.items():
+        scale = np.max(np.abs(o64))
+        print(f"{label} {k}: max|d| = {d.max():.3e} ({d.max() / scale:.1e} of max), "
+              f"max sigma_emp = {sig.max():.3e}, max |d|/sigma = {np.max(d / np.maximum(sig, 1e-300)):.1e}",
+              flush=True)
+        assert d.max() <= 1e-4 * scale, (label, k)
+        where = sig >= 1e-3 * sig.max()
+        assert np.all(d[where] <= 0.01 * sig[where]), (label, k, np.max(d[where] / sig[where]))
+
+
+def test_ring18_fp32_error_far_below_seed_spread(env):
+    torch, ftlm, driver = env
+    ref = json.load(open(os.path.join(GOLDEN, "ring18_r8.json")))
+    n = ref["n_sites"]
+    temps = np.asarray(ref["temps"])
+    out = _fp32_vs_spread(ftlm, driver, n, graphs.j1j2_ring(n, 1.0, ref["j2"]), ref["n_ups"], ref["R"], ref["M"],
+                          ref["seed"], ref, temps)
+    _check(out, "ring18 R=8")
+
+
+def test_square4x6_fp32_error_far_below_seed_spread(env):
+    torch, ftlm, driver = env
+    ref = json.load(open(os.path.join(GOLDEN, "square4x6_r2.json")))
+    n = ref["n_sites"]
+    temps = np.asarray(ref["temps"])
+    n_ups = [s["n_up"] for s in ref["sectors"]]
+    out = _fp32_vs_spread(ftlm, driver, n, [tuple(b) for b in ref["bonds"]], n_ups, 2, ref["M"], ref["seed"], ref,
+                          temps)
+    _check(out, "square4x6 R=2")
+
+
+def test_ghost_clusters_fp32_and_fp64(env):
+    """Same start vector, 150 steps in the N = 16 S^z = 0 sector (D = 12870)
+    of a J1-J2 ring: the low end converges early and repeats as ghosts. Each
+    weighted cluster of the FP64 run has an FP32 counterpart at the same
+    energy with the same total weight (Sec. 3.2, Fig. 5)."""
+    torch, ftlm, driver = env
+    n, n_up, M = 16, 8, 150
+    g = ftlm.Graph(n, graphs.j1j2_ring(n, 1.0, 0.3))
+    sec = ftlm.Sector(n, n_up, ftlm.CR)
+    res = {}
+    for dt in (ftlm.F32, ftlm.F64):
+        a, b, s = ftlm.lanczos(sec, g, 9, 0, 1, M, ftlm.GAUSS, dt)
+        res[dt] = ftlm.ghosts(a[0], b[0], int(s[0]), c_tau=1.0)
+        print(f"dtype {dt}: steps {int(s[0])}, ghosts {int(res[dt]['ghost'].sum())}, "
+              f"clusters {len(res[dt]['cluster_weight'])}, tau {res[dt]['tau']:.2e}", flush=True)
+    g64, g32 = res[ftlm.F64], res[ftlm.F32]
+    assert g32["ghost"].sum() >= g64["ghost"].sum()
+    # the weighted clusters of the FP64 run below the middle of the spectrum
+    mid = 0.5 * (g64["theta"][0] + g64["theta"][-1])
+    for c, w in enumerate(g64["cluster_weight"]):
+        th = g64["theta"][g64["cluster"] == c]
+        if w < 1e-6 or th.mean() > mid:
+            continue
+        near = np.abs(g32["theta"] - th.mean()) <= max(1e-4, 10 * g64["tau"])
+        assert near.any(), th
+        w32 = g32["weight"][near].sum()
+        assert abs(w32 - w) <= 1e-4 * max(w, 1e-3), (th.mean(), w, w32)

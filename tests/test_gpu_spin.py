@@ -1,0 +1,187 @@
+"""General local spin s on the GPU (Sec. 2, Eqs. 11-17), through the C ABI,
+against the general-spin oracle (oracle/spin.py):
+
+* sector dimensions (Eq. 15) and the stored tables (basis, compressed lookup
+  table over the d^N labels) bit for bit;
+* rank and unrank bit for bit, exhaustively, in both index maps, including
+  labels outside the sector and outside [0, d^N);
+* neighbour lists (both ladder terms of every bond) bit for bit;
+* H.x in FP64 and FP32 for 1, 2, 4 and 8 columns against FP64 rows, on
+  sectors spanning many row tiles with a ragged last tile;
+* exact-trace FTLM (unit start vectors, R = D) equal to exact
+  diagonalization of the dense Kronecker-product Hamiltonian at s = 1;
+* the spin-1 icosahedron FTLM over all M >= 0 sectors (R = 4, M = 40)
+  against the oracle's FP64 run with the same start vectors
+  (tests/golden/icosahedron_s1.json).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ed_spin
+from oracle import spin as sp
+from ftlm_inputs import graphs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+NONE = np.uint64(np.iinfo(np.uint64).max)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_26261_amd import driver, ftlm
+    return torch, ftlm, driver
+
+
+CASES = [(8, 2), (6, 3), (5, 4), (4, 6)]
+
+
+@pytest.mark.parametrize("n,two_s", CASES)
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rank_unrank_tables_exhaustive(env, n, two_s, mode):
+    torch, ftlm, _ = env
+    d = two_s + 1
+    space = np.arange(d ** n, dtype=np.uint64)
+    for a in range(n * two_s + 1):
+        print(f"spin case N={n} 2s={two_s} A={a} mode={mode}", flush=True)
+        want = sp.basis(n, two_s, a)
+        assert ftlm.sector_info_spin(n, two_s, a)[0] == len(want)
+        sec = ftlm.Sector(n, a, mode, two_s=two_s)
+        assert sec.dim == len(want)
+        idx = torch.arange(len(want) + 3, dtype=torch.int64, device="cuda")
+        lab = torch.empty_like(idx)
+        ftlm.unrank(sec, idx, lab)
+        got = lab.cpu().numpy().view(np.uint64)
+        np.testing.assert_array_equal(got[:len(want)], want)
+        assert np.all(got[len(want):] == NONE)
+        labels = np.concatenate([space, np.array([d ** n, d ** n + 7, 2 ** 40], dtype=np.uint64)])
+        lt = torch.from_numpy(labels.view(np.int64)).cuda()
+        out = torch.empty_like(lt)
+        ftlm.rank(sec, lt, out)
+        r = out.cpu().numpy().view(np.uint64)
+        expect = np.full(labels.size, NONE, dtype=np.uint64)
+        expect[want.astype(np.int64)] = np.arange(len(want), dtype=np.uint64)
+        np.testing.assert_array_equal(r, expect)
+        if mode == ftlm.CLT:
+            nb = (d ** n + 31) // 32
+            mask, prefix = ftlm.clt_export(sec, nb)
+            m_o, p_o = sp.clt(want, n, two_s)
+            np.testing.assert_array_equal(mask, m_o)
+            np.testing.assert_array_equal(prefix, p_o)
+
+
+@pytest.mark.parametrize("n,two_s", [(8, 2), (6, 3), (5, 4)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_neighbors_exhaustive(env, n, two_s, mode):
+    torch, ftlm, _ = env
+    rng = np.random.default_rng(n + two_s)
+    bonds = graphs.random_cluster(n, rng)
+    g = ftlm.Graph(n, bonds)
+    for a in range(n * two_s + 1):
+        b = sp.basis(n, two_s, a)
+        sec = ftlm.Sector(n, a, mode, two_s=two_s)
+        out = torch.empty(len(b) * 2 * g.n_bonds, dtype=torch.int64, device="cuda")
+        ftlm.neighbors(sec, g, 0, len(b), out)
+        got = out.cpu().numpy().view(np.uint64).reshape(len(b), 2 * g.n_bonds)
+        np.testing.assert_array_equal(got, sp.neighbors(two_s, bonds, b, 0, len(b)))
+
+
+@pytest.mark.parametrize("n,two_s,a", [(12, 2, 12), (9, 3, 13), (8, 4, 16), (12, 2, 17)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_hv_against_oracle(env, n, two_s, a, mode):
+    """Many row tiles with a ragged tail: D = 73,789 (spin-1 icosahedron,
+    M = 0), 30,276 (9 sites, s = 3/2, A = 13), 38,165 (8 sites, s = 2, A =
+    16), 16,236 (spin-1 icosahedron, M = 5)."""
+    torch, ftlm, _ = env
+    rng = np.random.default_rng(n * 100 + a)
+    bonds = graphs.icosahedron() if n == 12 else graphs.random_cluster(n, rng)
+    g = ftlm.Graph(n, bonds)
+    b = sp.basis(n, two_s, a)
+    sec = ftlm.Sector(n, a, mode, two_s=two_s)
+    assert sec.dim == len(b) and len(b) % 256 != 0
+    for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
+        for nv in (1, 2, 4, 8):
+            x = torch.randn((len(b), nv) if nv > 1 else (len(b),), dtype=dtype, device="cuda")
+            y = torch.empty_like(x)
+            ftlm.hv(sec, g, x, y)
+            xs = x.double().cpu().numpy().reshape(len(b), -1)
+            got = y.double().cpu().numpy().reshape(len(b), -1)
+            for c in range(nv):
+                want = sp.hv(n, two_s, bonds, xs[:, c], b)
+                rel = np.linalg.norm(got[:, c] - want) / np.linalg.norm(want)
+                assert rel <= tol, (dtype, nv, c, rel)
+
+
+def test_exact_trace_ftlm_equals_ed(env):
+    torch, ftlm, driver = env
+    n, two_s = 5, 2
+    bonds = [(0, 1, 1.0), (1, 2, 0.8), (2, 3, 1.2), (3, 4, 0.9), (4, 0, 1.1), (0, 2, 0.35)]
+    temps = np.geomspace(0.1, 10, 30)
+    recs = []
+    for a in range(n * two_s // 2, n * two_s + 1):
+        d = ftlm.sector_info_spin(n, two_s, a)[0]
+        for mode in (ftlm.CR,):
+            th, rr = driver.run(n, bonds, [a], d, d, 1, ftlm.UNIT, dtype=ftlm.F64, mode=mode, temps=temps,
+                                two_s=two_s)
+            recs += rr
+    th = ftlm.thermo(n, recs, temps, 1.0)
+    h = ed_spin.hamiltonian(n, two_s, bonds)
+    ev, m2 = [], []
+    for a in range(n * two_s + 1):
+        blk, _ = ed_spin.sector_block(h, n, two_s, a)
+        e = np.linalg.eigvalsh(blk)
+        ev.append(e)
+        m2.append(np.full(len(e), (a - 0.5 * n * two_s) ** 2))
+    ev, m2 = np.concatenate(ev), np.concatenate(m2)
+    e0 = ev.min()
+    for k, T in enumerate(temps):
+        w = np.exp(-(ev - e0) / T)
+        z = w.sum()
+        E = (w * ev).sum() / z
+        C = ((w * ev ** 2).sum() / z - E ** 2) / T ** 2
+        chi = (w * m2).sum() / z / T
+        assert abs(th["E"][k] - E) < 1e-8 * max(1, abs(E))
+        assert abs(th["C"][k] - C) < 1e-7 * max(1, C)
+        assert abs(th["chi"][k] - chi) < 1e-8 * max(1, chi)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_icosahedron_s1_all_sectors_against_oracle(env, mode):
+    torch, ftlm, driver = env
+    path = os.path.join(GOLDEN, "icosahedron_s1.json")
+    ref = json.load(open(path))
+    n, two_s, R, M = ref["n_sites"], ref["two_s"], ref["R"], ref["M"]
+    bonds = [tuple(b) for b in ref["bonds"]]
+    temps = np.asarray(ref["temps"])
+    a_list = [s["a"] for s in ref["sectors"]]
+    out = {}
+    for dtype in (ftlm.F64, ftlm.F32):
+        th, recs = driver.run(n, bonds, a_list, R, M, ref["seed"], ftlm.PM1, dtype=dtype, mode=mode, temps=temps,
+                              two_s=two_s)
+        out[dtype] = th
+        for rec, sref in zip(recs, ref["sectors"]):
+            assert rec["dim"] == sref["dim"]
+            for smp in sref["samples"]:
+                r = smp["r"]
+                assert rec["steps"][r] == smp["steps"]
+                if dtype == ftlm.F64:
+                    # the first steps agree to rounding; later ones drift apart with the
+                    # loss of orthogonality (Sec. 3.2)
+                    np.testing.assert_allclose(rec["alpha"][r, :10], smp["alpha"][:10], rtol=0, atol=1e-9)
+                    np.testing.assert_allclose(rec["beta"][r, :10], smp["beta"][:10], rtol=0, atol=1e-9)
+                else:
+                    assert abs(rec["alpha"][r, 0] - smp["alpha"][0]) < 1e-5 * (1 + abs(smp["alpha"][0]))
+    for k in ("E", "C", "chi"):
+        o = np.asarray(ref[k])
+        scale = np.abs(o).max()
+        assert np.max(np.abs(out[ftlm.F64][k] - o)) <= 1e-8 * scale, k
+        d32 = np.max(np.abs(out[ftlm.F32][k] - o))
+        print(f"mode {mode} {k}: FP32 max |d| = {d32:.2e} ({d32 / scale:.1e} of max)", flush=True)
+        assert d32 <= 1e-4 * scale, k

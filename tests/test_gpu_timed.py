@@ -73,8 +73,8 @@ def _check_columns(got, rows, n, n_up, bonds, seed, dist):
         assert d.max() <= 1e-4, (c, d.max(), rows[d.argmax()])
 
 
-@pytest.mark.parametrize("nvec", [1, 4, 8, 10, 12, 16, 20, 32])
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode,nvec", [(m, b) for m in (0, 1) for b in (1, 4, 8, 10, 12, 16, 20, 32)]
+                         + [(m, b) for m in (2, 3) for b in (1, 8, 12)])
 def test_hv_n30_every_column(env, mode, nvec):
     torch, ftlm = env
     n, n_up, seed = 30, 15, 2
@@ -133,7 +133,9 @@ def test_icosidodecahedron_every_chain_first_steps(env, batch):
     ref = json.load(open(path))
     n, n_up = ref["n_sites"], ref["n_up"]
     g = ftlm.Graph(n, [tuple(b) for b in ref["bonds"]])
-    for mode in (ftlm.CLT, ftlm.CR):
+    # the stored-map variants (full table, Lin's tables) at the autotuned split
+    modes = (ftlm.CLT, ftlm.CR) + ((ftlm.FULL, ftlm.LIN) if batch == 12 else ())
+    for mode in modes:
         sec = ftlm.Sector(n, n_up, mode)
         alpha = np.zeros((20, 3))
         beta = np.zeros((20, 3))

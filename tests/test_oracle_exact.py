@@ -338,3 +338,19 @@ def test_hv_rows_on_streamed_vectors():
         rows = np.array([0, 17, 1000, len(b) - 1], dtype=np.uint64)
         np.testing.assert_allclose(oracle.hv_rows_stream(n, n_up, bonds, 8, 3, dist, rows),
                                    oracle.hv(n, n_up, bonds, x, b)[rows.astype(int)], rtol=0, atol=1e-12)
+
+
+def test_paper_cpu_method_equals_the_oracle():
+    """The batched B = 8 CLT CPU kernel timed by the CPU baseline (the paper's
+    CPU method, not an oracle definition) computes the oracle's H.x."""
+    from oracle import paper_cpu
+    n, n_up = 16, 7
+    bonds = graphs.random_cluster(16, np.random.default_rng(8))
+    b = oracle.basis(n, n_up)
+    mask, prefix = oracle.clt(b, n)
+    x = np.random.default_rng(9).standard_normal((len(b), 8))
+    got = paper_cpu.hv_clt_b8(bonds, b, mask, prefix, x)
+    for c in range(8):
+        np.testing.assert_allclose(got[:, c], oracle.hv(n, n_up, bonds, x[:, c], b), rtol=0, atol=1e-12)
+    part = paper_cpu.hv_clt_b8(bonds, b, mask, prefix, x, row0=100, nrows=333)
+    np.testing.assert_array_equal(part, got[100:433])
