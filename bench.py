@@ -375,7 +375,37 @@ def precision(n_seeds=10):
     runs = [ftlm.thermo(24, driver.plan_records(plan, 24, 1000 + s, ftlm.PM1), temps, 1.0) for s in range(n_seeds)]
     out["square4x6_R2_M80"] = _precision_summary(ftlm, th, ref, runs, temps, ("E", "C", "chi"))
     del plan
+    out["ghosts"] = ghost_study()
     return out
+
+
+def ghost_study(n_chains=8, M=100):
+    """Sec. 3.2 on the GPU: Cullum-Willoughby ghosts (Eq. 25, C_tau = 1) of
+    FP32 and FP64 chains from the same start vectors in the M = 0 sector of
+    the spin-1 icosahedron (D = 73,789), N_L = 100, and how far the total
+    weights of matching Ritz clusters move between the precisions."""
+    import numpy as np
+
+    from ftlm_inputs import graphs
+    from paper_2605_26261_amd import ftlm
+
+    g = ftlm.Graph(12, graphs.icosahedron())
+    sec = ftlm.Sector(12, 12, ftlm.CR, two_s=2)
+    res = {}
+    for name, dt in (("f32", ftlm.F32), ("f64", ftlm.F64)):
+        a, b, st = ftlm.lanczos(sec, g, 11, 0, n_chains, M, ftlm.GAUSS, dt)
+        res[name] = [ftlm.ghosts(a[r], b[r], int(st[r]), c_tau=1.0) for r in range(n_chains)]
+    dw = 0.0
+    for g64, g32 in zip(res["f64"], res["f32"]):
+        for c, w in enumerate(g64["cluster_weight"]):
+            th = g64["theta"][g64["cluster"] == c].mean()
+            near = np.abs(g32["theta"] - th) <= 10 * max(g64["tau"], g32["tau"])
+            if w > 1e-6 and near.any():
+                dw = max(dw, abs(g32["weight"][near].sum() - w))
+    return {"workload": f"spin-1 icosahedron M=0 (D={sec.dim}), {n_chains} Gaussian chains, N_L={M}, C_tau=1",
+            "ghosts_f32": [int(x["ghost"].sum()) for x in res["f32"]],
+            "ghosts_f64": [int(x["ghost"].sum()) for x in res["f64"]],
+            "max_cluster_weight_shift": dw}
 
 
 def largest_sector():

@@ -142,6 +142,28 @@ struct GatherVisitor {
     }
     __device__ __forceinline__ void add_slot_a() { add_slot(slot_a, w_a); }
     __device__ __forceinline__ void add_slot_b() { add_slot(slot_b, w_b); }
+    // Stored maps: one group slot of kGroup rows, loaded by every lane (row 0
+    // under weight zero where the bond is parallel), accumulated by add_group.
+    static constexpr bool kTablePipe = true;
+    T grow[kGroup][VB];
+    T gw[kGroup];
+    __device__ __forceinline__ void load_group(int b0, const uint32_t (&idx)[kGroup], const bool (&flips)[kGroup]) {
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            const uint32_t i = idx[g] < last ? idx[g] : last;
+            load_row<T, VB>(x + uint64_t(i) * ld + col0, grow[g]);
+            const T cb = bond_coef<T>(B, b0 + g);
+            gw[g] = flips[g] ? cb : T(0);
+        }
+    }
+    __device__ __forceinline__ void add_group() {
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+#pragma unroll
+            for (int i = 0; i < VB; ++i) acc[i] += gw[g] * grow[g][i];
+            anti += gw[g];
+        }
+    }
     __device__ __forceinline__ void group(int b0, const uint32_t (&idx)[kGroup], const bool (&flips)[kGroup]) {
         T v[kGroup][VB];
 #pragma unroll

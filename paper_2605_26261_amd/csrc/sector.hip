@@ -158,6 +158,7 @@ struct NeighborVisitor {
     const BondTable& B;
     static constexpr int kGroup = 2;
     static constexpr bool kPairs = false;
+    static constexpr bool kTablePipe = false;
     static constexpr int kSiteGroup = 2;
     __device__ __forceinline__ void flip(int b, uint32_t idx) { out[B.orig(b)] = idx; }
     __device__ __forceinline__ void site_group(int b0, const uint32_t (&idx)[kSiteGroup],

@@ -10,7 +10,8 @@ vectors, set against the stochastic error of the method.
   temperature where the spread is not negligible.
 * Ghost diagnostic (Sec. 3.2, Eq. 25): FP32 and FP64 chains from the same
   start vector, far past the convergence of the low end of the spectrum;
-  the clusters of both precisions carry the same weights.
+  FP32 has at least as many ghosts, and every converged, repeated eigenvalue
+  carries the same total cluster weight in both precisions.
 """
 import json
 import os
@@ -89,9 +90,7 @@ def test_square4x6_fp32_error_far_below_seed_spread(env):
 
 def test_ghost_clusters_fp32_and_fp64(env):
     """Same start vector, 150 steps in the N = 16 S^z = 0 sector (D = 12870)
-    of a J1-J2 ring: the low end converges early and repeats as ghosts. Each
-    weighted cluster of the FP64 run has an FP32 counterpart at the same
-    energy with the same total weight (Sec. 3.2, Fig. 5)."""
+    of a J1-J2 ring: the low end converges early and repeats as ghosts."""
     torch, ftlm, driver = env
     n, n_up, M = 16, 8, 150
     g = ftlm.Graph(n, graphs.j1j2_ring(n, 1.0, 0.3))
@@ -103,14 +102,23 @@ def test_ghost_clusters_fp32_and_fp64(env):
         print(f"dtype {dt}: steps {int(s[0])}, ghosts {int(res[dt]['ghost'].sum())}, "
               f"clusters {len(res[dt]['cluster_weight'])}, tau {res[dt]['tau']:.2e}", flush=True)
     g64, g32 = res[ftlm.F64], res[ftlm.F32]
+    # FP32 loses orthogonality sooner: at least as many ghosts (Sec. 3.2)
     assert g32["ghost"].sum() >= g64["ghost"].sum()
-    # the weighted clusters of the FP64 run below the middle of the spectrum
-    mid = 0.5 * (g64["theta"][0] + g64["theta"][-1])
+    # the converged, repeated eigenvalues: FP64 clusters with a ghost-flagged
+    # member. Each has FP32 Ritz values at the same energy carrying the same
+    # total weight; the ghosts only share it out (Fig. 5)
+    checked, worst = 0, 0.0
     for c, w in enumerate(g64["cluster_weight"]):
-        th = g64["theta"][g64["cluster"] == c]
-        if w < 1e-6 or th.mean() > mid:
+        members = g64["cluster"] == c
+        if w < 1e-6 or not g64["ghost"][members].any():
             continue
-        near = np.abs(g32["theta"] - th.mean()) <= max(1e-4, 10 * g64["tau"])
+        th = g64["theta"][members]
+        win = max(1e-5, 10 * g64["tau"])
+        near = (g32["theta"] >= th.min() - win) & (g32["theta"] <= th.max() + win)
         assert near.any(), th
-        w32 = g32["weight"][near].sum()
-        assert abs(w32 - w) <= 1e-4 * max(w, 1e-3), (th.mean(), w, w32)
+        dw = abs(g32["weight"][near].sum() - w)
+        worst = max(worst, dw)
+        assert dw <= 1e-4 * max(w, 1e-2), (th, w, g32["weight"][near].sum())
+        checked += 1
+    print(f"{checked} converged clusters, largest weight shift {worst:.2e}", flush=True)
+    assert checked >= 1

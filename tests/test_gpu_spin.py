@@ -174,8 +174,9 @@ def test_icosahedron_s1_all_sectors_against_oracle(env, mode):
                 if dtype == ftlm.F64:
                     # the first steps agree to rounding; later ones drift apart with the
                     # loss of orthogonality (Sec. 3.2)
-                    np.testing.assert_allclose(rec["alpha"][r, :10], smp["alpha"][:10], rtol=0, atol=1e-9)
-                    np.testing.assert_allclose(rec["beta"][r, :10], smp["beta"][:10], rtol=0, atol=1e-9)
+                    k = min(10, smp["steps"])  # a small sector's chain stops early
+                    np.testing.assert_allclose(rec["alpha"][r, :k], smp["alpha"][:k], rtol=0, atol=1e-9)
+                    np.testing.assert_allclose(rec["beta"][r, :k], smp["beta"][:k], rtol=0, atol=1e-9)
                 else:
                     assert abs(rec["alpha"][r, 0] - smp["alpha"][0]) < 1e-5 * (1 + abs(smp["alpha"][0]))
     for k in ("E", "C", "chi"):
