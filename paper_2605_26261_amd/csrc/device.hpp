@@ -177,12 +177,9 @@ struct TableMap<kModeLin> {
 //   v.flip(b, idx)  for an antiparallel bond b (b in the sorted order), and
 //   v.par(b)        for a parallel one;
 // or, when the visitor takes groups (V::kGroup > 1), v.group(b0, idx, flips)
-// for kGroup consecutive bonds at a time. In CR (cr_bonds below) a
-// visitor takes up to V::kSiteGroup bonds of one lower site at a time, as
-// v.site_group(b0, idx, flips, count); cr_bonds_pairs keeps two such slots
-// in flight. A group's table loads and then its row
-// gathers are in flight together; lanes whose bond is parallel issue neither,
-// and the visitor weighs them by zero.
+// for kGroup consecutive bonds at a time. A group's table loads and then its
+// row gathers are in flight together; lanes whose bond is parallel issue
+// neither, and the visitor weighs them by zero.
 template <typename Map, typename V>
 __device__ __forceinline__ void table_bonds(uint32_t n, const BondTable& B, const Map& map, V& v) {
     int b = 0;
@@ -206,68 +203,6 @@ __device__ __forceinline__ void table_bonds(uint32_t n, const BondTable& B, cons
         }
     }
     for (; b < B.n_bonds; ++b) {
-        const uint32_t si = (n >> B.lo(b)) & 1u, sj = (n >> B.hi(b)) & 1u;
-        if (si != sj) {
-            const uint32_t m = n ^ ((1u << B.lo(b)) | (1u << B.hi(b)));
-            v.flip(b, map.index(map.fetch(m), m));
-        } else {
-            v.par(b);
-        }
-    }
-}
-
-// table_bonds for a visitor that overlaps a group's table loads with the row
-// gathers of the group before it (V::kTablePipe): the entries of group k + 1
-// are in flight while the rows of group k are gathered and accumulated. Both
-// kinds of load are issued by every lane (a lane whose bond is parallel looks
-// up its own label and gathers row 0, under weight zero), so no load sits
-// under a branch and the compiler waits for exactly the older loads. The
-// groups and the order of every accumulation are those of table_bonds.
-template <typename Map, typename V>
-__device__ __forceinline__ void table_bonds_pipelined(uint32_t n, const BondTable& B, const Map& map, V& v) {
-    constexpr int G = V::kGroup;
-    const int nb = B.n_bonds;
-    const int ng = nb / G;
-    struct Grp {
-        uint32_t m[G];
-        bool anti[G];
-        typename Map::Entry e[G];
-    };
-    auto fetch = [&](int b0, Grp& q) {
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const uint32_t lo = B.lo(b0 + g), hi = B.hi(b0 + g);
-            q.anti[g] = ((n >> lo) & 1u) != ((n >> hi) & 1u);
-            q.m[g] = q.anti[g] ? n ^ ((1u << lo) | (1u << hi)) : n;
-            q.e[g] = map.fetch(q.m[g]);
-        }
-    };
-    auto gather = [&](int b0, const Grp& q) {
-        uint32_t idx[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) idx[g] = q.anti[g] ? map.index(q.e[g], q.m[g]) : 0u;
-        v.load_group(b0, idx, q.anti);
-    };
-    int k = 0;
-    if (ng > 0) {
-        Grp qa, qb;
-        fetch(0, qa);
-        for (; k + 2 <= ng; k += 2) {
-            gather(k * G, qa);
-            fetch((k + 1) * G, qb);
-            v.add_group();
-            gather((k + 1) * G, qb);
-            // the next pair's first group, or (past the end) group 0 again
-            fetch(k + 2 < ng ? (k + 2) * G : 0, qa);
-            v.add_group();
-        }
-        if (k < ng) {
-            gather(k * G, qa);
-            v.add_group();
-            ++k;
-        }
-    }
-    for (int b = k * G; b < nb; ++b) {
         const uint32_t si = (n >> B.lo(b)) & 1u, sj = (n >> B.hi(b)) & 1u;
         if (si != sj) {
             const uint32_t m = n ^ ((1u << B.lo(b)) | (1u << B.hi(b)));
@@ -319,34 +254,11 @@ __device__ __forceinline__ L cr_bonds(uint32_t t, L n_in, int n_up, const BondTa
         }
         ylds[p * 64] = Y;
         const int end = int(B.ends[p]);
-        if constexpr (V::kSiteGroup > 1) {
-            // the bonds whose lower site is p, V::kSiteGroup at a time: their
-            // gathers go out together before any of them is consumed
-            constexpr int G = V::kSiteGroup;
-            for (; b < end; b += G) {
-                const int cnt = end - b < G ? end - b : G;
-                uint32_t idx[G];
-                bool anti[G];
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    anti[g] = false;
-                    idx[g] = t;
-                    if (g < cnt) {
-                        const uint32_t hb = B.hi(b + g);
-                        anti[g] = uint32_t((n >> hb) & 1) != uint32_t(one);
-                        if (anti[g]) idx[g] = t + X + ylds[hb * 64];
-                    }
-                }
-                v.site_group(b, idx, anti, cnt);
-            }
-            b = end;
-        } else {
-            for (; b < end; ++b) {
-                const uint32_t hb = B.hi(b);
-                const uint32_t shi = uint32_t((n >> hb) & 1);
-                if (shi != uint32_t(one)) v.flip(b, t + X + ylds[hb * 64]);
-                else v.par(b);
-            }
+        for (; b < end; ++b) {
+            const uint32_t hb = B.hi(b);
+            const uint32_t shi = uint32_t((n >> hb) & 1);
+            if (shi != uint32_t(one)) v.flip(b, t + X + ylds[hb * 64]);
+            else v.par(b);
         }
     }
     return n;
@@ -439,8 +351,7 @@ __device__ __forceinline__ L visit_row(uint32_t t, int n_up, const BondTable& B,
                                        const uint32_t* __restrict__ basis, const Map& map, uint32_t* ylds, V& v) {
     if constexpr (MODE != kModeCr) {
         const uint32_t n = *gptr(basis + t);
-        if constexpr (V::kTablePipe) table_bonds_pipelined(n, B, map, v);
-        else table_bonds(n, B, map, v);
+        table_bonds(n, B, map, v);
         return L(n);
     } else {
         if constexpr (V::kPairs) return cr_bonds_pairs<L>(t, n_up, B, C, ylds, v);

@@ -114,7 +114,8 @@ size_t layout_state(uint64_t dim, int R, int dtype, size_t off, SectorState& st)
     const size_t es = dtype == FTLM_F32 ? 4 : 8;
     st.u0 = off; off = align256(off + size_t(dim) * size_t(R) * es);
     st.u1 = off; off = align256(off + size_t(dim) * size_t(R) * es);
-    st.partials = off; off = align256(off + size_t(rows_grid(uint32_t(dim))) * size_t(R) * sizeof(double));
+    const size_t slots = std::max(rows_grid(uint32_t(dim)), sector_items(uint32_t(dim)));
+    st.partials = off; off = align256(off + slots * size_t(R) * sizeof(double));
     st.chains = off; off = align256(off + size_t(R) * sizeof(Chain));
     st.alpha = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
     st.beta = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
@@ -129,8 +130,9 @@ size_t layout_state(uint64_t dim, int R, int dtype, size_t off, SectorState& st)
 // Fills job.secs for sectors whose tables are described by `devs` and whose
 // state sits at `states` inside `base`. Each graph contributes its bond table
 // in the caller's labels. The descriptor array goes to `dev_secs`
-// (device). Blocks: each sector gets rows_grid(D) blocks starting at a
-// multiple of 8.
+// (device). Blocks of the static-grid kernels: each sector gets rows_grid(D)
+// blocks starting at a multiple of 8; the persistent H.x splits it into
+// sector_items(D) work items.
 void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::vector<SectorState>& states,
                 void* base, int R, int M, int dtype, SecWork* dev_secs, const std::vector<const ftlm_graph*>& graphs,
                 const std::vector<BondTable*>& dev_tables, const std::vector<int>& graph_of) {
@@ -151,7 +153,7 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
     }
     job.secs.assign(devs.size(), SecWork{});
     job.key_ptrs.clear();
-    uint32_t block = 0;
+    uint32_t block = 0, items = 0;
     size_t lds = 0;
     job.max_steps = 0;
     for (size_t i = 0; i < devs.size(); ++i) {
@@ -171,6 +173,8 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
         w.keys = at<uint64_t>(base, st.keys);
         job.key_ptrs.push_back(at<uint64_t>(base, st.keys));
         w.G = rows_grid(devs[i].dim);
+        w.items = sector_items(devs[i].dim);
+        items += w.items;
         w.block0 = block;
         block = (block + w.G + 7) & ~7u;
         w.m_eff = int(std::min<uint64_t>(uint64_t(M), devs[i].dim));
@@ -178,6 +182,7 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
         lds = std::max(lds, hv_lds_bytes(devs[i]));
     }
     job.grid = int(block);
+    job.items = int(items);
     job.lds = lds;
     job.chunks = job_chunks(job, max_launch_width(job.two_s));
 }

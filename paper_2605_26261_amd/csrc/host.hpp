@@ -133,6 +133,7 @@ P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(b
 // that reads them has been synchronized.
 struct LanczosJob {
     int nsec = 0, R = 0, dtype = 0, mode = 0, n_sites = 0, grid = 0, two_s = 1;
+    int items = 0;                       // work items of the persistent H.x, all sectors
     size_t lds = 0;
     std::vector<SecWork> secs;           // host copies of the descriptors
     std::vector<uint64_t> keys;          // [nsec][R] stream keys of the run
@@ -149,6 +150,7 @@ struct LanczosJob {
         a.secs = dev_secs;
         a.nsec = nsec;
         a.grid = grid;
+        a.items = items;
         a.ld = uint64_t(R);
         a.dtype = dtype;
         a.eps = dtype == FTLM_F32 ? 1e-6 : 1e-12;

@@ -93,11 +93,14 @@ struct GatherVisitor {
     // (Lanczos step at N = 30): 8 at one column (9.0 -> 8.3 ms against 4),
     // 6 at 8 columns, 3 at 12, 2 from 16 up, 4 elsewhere.
     static constexpr int kGroup = VB == 1 ? 8 : VB == 8 ? 6 : VB == 12 ? 3 : VB >= 16 ? 2 : 4;
-    // CR: the bonds in slots of kSiteGroup, two slots in flight (cr_bonds_pairs)
-    // for blocks of up to 20 columns; wider blocks take one bond at a time
-    // (flip / par).
-    static constexpr bool kPairs = VB <= 20;
-    static constexpr int kSiteGroup = VB >= 10 ? 1 : 2;
+    // CR: up to 8 columns, the bonds in slots of kSiteGroup with two slots in
+    // flight (cr_bonds_pairs); wider blocks take one bond at a time (flip /
+    // par). Lanczos step at N = 30: one column 15.1 -> 9.6 ms; from 10
+    // columns up the two slots were slower (12 columns 36.6 -> 41.5 ms):
+    // every lane then loads a full row per bond, parallel lanes included,
+    // and the kernel is bound by the traffic, not the latency, of its gathers.
+    static constexpr bool kPairs = VB <= 8;
+    static constexpr int kSiteGroup = 2;
     // The two slots: rows of x and their weights (J_b / 2 for a flip, else 0).
     // Every lane loads, so the loads are not under a branch and the compiler
     // can wait for exactly the older slot: a lane whose bond is parallel
@@ -142,28 +145,6 @@ struct GatherVisitor {
     }
     __device__ __forceinline__ void add_slot_a() { add_slot(slot_a, w_a); }
     __device__ __forceinline__ void add_slot_b() { add_slot(slot_b, w_b); }
-    // Stored maps: one group slot of kGroup rows, loaded by every lane (row 0
-    // under weight zero where the bond is parallel), accumulated by add_group.
-    static constexpr bool kTablePipe = true;
-    T grow[kGroup][VB];
-    T gw[kGroup];
-    __device__ __forceinline__ void load_group(int b0, const uint32_t (&idx)[kGroup], const bool (&flips)[kGroup]) {
-#pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-            const uint32_t i = idx[g] < last ? idx[g] : last;
-            load_row<T, VB>(x + uint64_t(i) * ld + col0, grow[g]);
-            const T cb = bond_coef<T>(B, b0 + g);
-            gw[g] = flips[g] ? cb : T(0);
-        }
-    }
-    __device__ __forceinline__ void add_group() {
-#pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-#pragma unroll
-            for (int i = 0; i < VB; ++i) acc[i] += gw[g] * grow[g][i];
-            anti += gw[g];
-        }
-    }
     __device__ __forceinline__ void group(int b0, const uint32_t (&idx)[kGroup], const bool (&flips)[kGroup]) {
         T v[kGroup][VB];
 #pragma unroll
@@ -296,44 +277,58 @@ __device__ __forceinline__ void stage_epilogue(T* ab, const Chain* chains) {
     }
 }
 
-// Publishes this block's <u_k, w> sums (per-wave FP64 sums in wsum) and, in
-// the sector's last block, sums the G partials of each column in block order
-// into alpha_k and the update coefficient.
+// The block's FP64 partials of <u_k, w> for its VB columns (wsum: one row of
+// VB per wave) into its slot of the sector's partials.
 template <int VB>
-__device__ __forceinline__ void alpha_tail(const SecWork& sw, const LanczosLaunch& a, const double* wsum,
-                                           double* red, uint32_t local, int* flag) {
+__device__ __forceinline__ void store_partials(const SecWork& sw, const LanczosLaunch& a, const double* wsum,
+                                               uint32_t slot) {
     __syncthreads();
     if (threadIdx.x < VB) {
         double t = 0.0;
         for (int w = 0; w < kWaves; ++w) t += wsum[w * VB + threadIdx.x];
-        sw.partials[size_t(local) * a.ld + a.col0 + threadIdx.x] = t;
+        sw.partials[size_t(slot) * a.ld + a.col0 + threadIdx.x] = t;
     }
-    if (last_block(sw.ticket, sw.G, flag)) {
+}
+
+// alpha_k of the launch's columns of one sector from its n partial slots.
+template <int VB>
+__device__ __forceinline__ void finish_alpha(const SecWork& sw, const LanczosLaunch& a, uint32_t n, double* red) {
+    double tot[VB];
+    grid_sum_cols<VB>(sw.partials, int(n), int(a.ld), int(a.col0), VB, red, tot);
+    if (threadIdx.x == 0) {
         for (int c = 0; c < VB; ++c) {
-            const double tot = grid_sum_col(sw.partials, int(sw.G), int(a.ld), int(a.col0) + c, red);
-            if (threadIdx.x == 0) {
-                Chain* ch = &sw.chains[a.col0 + c];
-                ch->alpha = ch->s_cur * tot;
-                ch->up_d = ch->alpha * ch->s_cur;
-                ch->up_f = float(ch->up_d);
-            }
+            Chain* ch = &sw.chains[a.col0 + c];
+            ch->alpha = ch->s_cur * tot[c];
+            ch->up_d = ch->alpha * ch->s_cur;
+            ch->up_f = float(ch->up_d);
         }
+    }
+}
+
+// Static-grid form (general-spin H.x, one block per slot): the block stores
+// its partials and the last block of the sector (ticket) sums them.
+template <int VB>
+__device__ __forceinline__ void alpha_tail(const SecWork& sw, const LanczosLaunch& a, const double* wsum,
+                                           double* red, uint32_t local, int* flag) {
+    store_partials<VB>(sw, a, wsum, local);
+    if (last_block(sw.ticket, sw.G, flag)) {
+        finish_alpha<VB>(sw, a, sw.G, red);
         if (threadIdx.x == 0) *sw.ticket = 0u;
     }
 }
 
 // First half of Lanczos step k over every sector of the launch (one sector,
 // all sectors of a plan, or a server round): w = H q_k - beta_{k-1} q_{k-1}
-// and the FP64 partials of <u_k, w>; the last block of each sector sums the
-// partials in block order into alpha_k (and the update coefficient). A sector
-// whose chains have all stopped is skipped.
+// and the FP64 partials of <u_k, w>, summed in slot order into alpha_k (and
+// the update coefficient). A sector whose chains have all stopped is skipped.
 //
-// With a work queue (a.queue) the grid is persistent, sized to the resident
-// workgroups: each workgroup takes (sector, block) items from its XCD's
-// counter and runs them one after the other, largest sectors first. An item
-// is exactly the work of one block of the one-block-per-item grid (same
-// tiles, same partial slot), so the reduction order, and every result, is
-// the same in both forms.
+// The grid is persistent, sized to the resident workgroups: each workgroup
+// takes (sector, item) pairs from its XCD's counter (queue_item) and runs
+// them one after the other, and each item stores its partials in its own
+// slot with plain stores. The last workgroup to leave (queue_exit, the one
+// device-scope fence of each workgroup) sums every sector's slots. Which
+// workgroup ran an item changes nothing: the tiles of an item, its partial
+// slot and the summation order depend on the sector's dimension only.
 template <typename L, int MODE, typename T, int VB>
 __global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(LanczosLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -343,20 +338,12 @@ __global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(LanczosLaunch a) {
     __shared__ T ab[2 * VB];
     const SecWork* secs = a.secs;
     const uint32_t xcd = blockIdx.x & 7u;
-    bool first_item = true;
     for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(a.queue + xcd, 1u);
+        __syncthreads();
         uint32_t local = 0;
-        int s;
-        if (a.queue) {
-            if (threadIdx.x == 0) next = atomicAdd(a.queue + xcd, 1u);
-            __syncthreads();
-            s = queue_item(secs, a.nsec, xcd, next, &local);
-            __syncthreads();  // every thread has read `next`
-        } else {
-            if (!first_item) break;
-            s = sector_of_block(secs, a.nsec, blockIdx.x, &local);
-        }
-        first_item = false;
+        const int s = queue_item(secs, a.nsec, xcd, next, &local);
+        __syncthreads();  // every thread has read `next`
         if (s < 0) break;
         const SecWork& sw = secs[s];
         if (sw.state[1] == 0) continue;
@@ -370,12 +357,16 @@ __global__ __launch_bounds__(kBlock) void hv_lanczos_kernel(LanczosLaunch a) {
         __syncthreads();
         const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
         T* y = static_cast<T*>(sw.u[step & 1]);
-        hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, ab, step == 1,
-                                              wsum);
-        alpha_tail<VB>(sw, a, wsum, lds.red, local, &flag);
+        hv_body<L, MODE, T, VB, kEpiLanczos>(S, B, lds, x, y, a.ld, a.col0, 0, S.dim, local, sw.items, ab,
+                                              step == 1, wsum);
+        store_partials<VB>(sw, a, wsum, local);
         __syncthreads();  // LDS (bonds, scalars, tables) is restaged by the next item
     }
-    if (a.queue) queue_exit(a.queue, gridDim.x);
+    if (queue_exit(a.queue, gridDim.x, &flag)) {
+        double* red = reinterpret_cast<double*>(smem);
+        for (int s = 0; s < a.nsec; ++s)
+            if (secs[s].state[1] != 0) finish_alpha<VB>(secs[s], a, secs[s].items, red);
+    }
 }
 
 // Dynamic LDS of the plain H.x at 20 and more FP32 columns: enough that two
@@ -413,11 +404,10 @@ hipError_t launch_lanczos_one(const LanczosLaunch& a, size_t lds, hipStream_t st
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
     }
-    int grid = a.grid;
-    if (a.queue) {
-        hipError_t e = persistent_grid(reinterpret_cast<const void*>(kern), lds, a.grid, &grid);
-        if (e != hipSuccess) return e;
-    }
+    if (!a.queue || a.items <= 0) return hipErrorInvalidValue;  // the queue counters are required
+    int grid = 0;
+    hipError_t e = persistent_grid(reinterpret_cast<const void*>(kern), lds, a.items, &grid);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kBlock), lds, st, a);
     return hipGetLastError();
 }

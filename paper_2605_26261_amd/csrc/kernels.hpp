@@ -94,17 +94,19 @@ struct HvLaunch {
 };
 
 // One sector of a Lanczos launch (one sector, all sectors of a plan, or the
-// active requests of a server round), in device memory. Its blocks are
-// [block0, block0 + G) of the launch grid, with G = rows_grid(D) so the
-// reduction order of every column depends on D only. Each sector carries its
-// own bond table and step counter, so sectors of different graphs at
-// different Lanczos steps can share a launch.
+// active requests of a server round), in device memory. In the kernels with a
+// static grid (start vectors, update, general-spin H.x) its blocks are
+// [block0, block0 + G) of the launch grid, with G = rows_grid(D); the
+// persistent spin-1/2 H.x splits it into `items` = sector_items(D) work
+// items. Both depend on D only, and so does the reduction order of every
+// column. Each sector carries its own bond table and step counter, so
+// sectors of different graphs at different Lanczos steps can share a launch.
 struct SecWork {
     SectorDev S;
     const BondTable* bonds;
     void* u[2];          // [D][ld] vector blocks; step k reads u_k from u[(k-1)&1]
     Chain* chains;       // [ld]
-    double* partials;    // [G][ld]
+    double* partials;    // [max(G, items)][ld]
     uint32_t* ticket;
     int32_t* state;      // [0] = current step k (1-based), [1] = chains still active
     double* alpha;       // [ld][kMaxSteps]
@@ -113,6 +115,7 @@ struct SecWork {
     uint64_t r0;         // sample index of column 0
     uint32_t G;
     uint32_t block0;
+    uint32_t items;      // work items of the persistent H.x
     int32_t m_eff;       // min(M, D)
 };
 
@@ -122,6 +125,7 @@ struct LanczosLaunch {
     const SecWork* secs;
     int nsec;
     int grid;            // total blocks (sum of the sectors' G, 8-aligned)
+    int items;           // work items of the persistent H.x (sum of the sectors' items)
     uint64_t ld;
     uint32_t col0;
     int vb;
@@ -207,6 +211,22 @@ __host__ __device__ inline uint32_t rows_grid(uint32_t nrows) {
     return (g + 7) & ~7u;
 }
 
+// Work items of a sector in the persistent Lanczos H.x, each with its own
+// slot of reduction partials: a multiple of 8 (an equal count per XCD), about
+// four row tiles per item, at most 16384. A workgroup runs several items, so
+// with many small items every workgroup ends within about one item of the
+// others whatever the kernel's occupancy; the count depends on the row count
+// only, so the reduction order, and every result, does not depend on the
+// launch width, the index map or the other sectors.
+__host__ __device__ inline uint32_t sector_items(uint32_t nrows) {
+    const uint32_t tiles = (nrows + kBlock - 1) / kBlock;
+    if (tiles < 8) return tiles == 0 ? 1u : tiles;
+    const uint32_t cap = 16384;
+    uint32_t g = (tiles + 3) / 4;
+    g = g < 8 ? 8 : (g < cap ? g : cap);
+    return (g + 7) & ~7u;
+}
+
 // Work item k of XCD x in a persistent launch: the sectors' blocks whose
 // index inside the sector is x mod 8, sector by sector in launch order (a
 // block index keeps its XCD, so the tile order of for_each_tile still gives
@@ -215,7 +235,7 @@ __host__ __device__ inline uint32_t rows_grid(uint32_t nrows) {
 __device__ __forceinline__ int queue_item(const SecWork* secs, int nsec, uint32_t xcd, uint32_t k,
                                           uint32_t* local) {
     for (int s = 0; s < nsec; ++s) {
-        const uint32_t G = secs[s].G;
+        const uint32_t G = secs[s].items;
         const uint32_t cnt = G > xcd ? (G - xcd + 7u) / 8u : 0u;
         if (k < cnt) {
             *local = xcd + 8u * k;
@@ -226,15 +246,28 @@ __device__ __forceinline__ int queue_item(const SecWork* secs, int nsec, uint32_
     return -1;
 }
 
-// Called by every block of a persistent launch after its last item: the last
-// block to get here zeroes the counters (every block has stopped taking items).
-__device__ __forceinline__ void queue_exit(uint32_t* q, uint32_t grid) {
+// Called by every block of a persistent launch after its last item. Every
+// thread's writes (outputs and reduction partials) are released, then the
+// block counts itself out; returns true in the last block to get here, with
+// every other block's writes visible to it, after it has zeroed the counters
+// for the next launch (every block has stopped taking items). These are the
+// only device-scope fences of the launch: on gfx950 such a fence writes back
+// and invalidates the XCD's L2, which a fence per work item would do
+// thousands of times while other workgroups still gather from it.
+__device__ __forceinline__ bool queue_exit(uint32_t* q, uint32_t grid, int* flag_lds) {
+    __threadfence();
+    __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
         const uint32_t done = atomicAdd(q + 8, 1u);
-        if (done == grid - 1u)
+        const bool last = done == grid - 1u;
+        if (last)
             for (int i = 0; i < kQueueWords; ++i) atomicExch(q + i, 0u);
+        *flag_lds = last ? 1 : 0;
     }
+    __syncthreads();
+    const bool last = *flag_lds != 0;
+    if (last) __threadfence();
+    return last;
 }
 
 // The sector owning block `b` of a multi-sector launch, by a wave-uniform

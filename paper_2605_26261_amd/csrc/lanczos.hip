@@ -108,12 +108,13 @@ __global__ __launch_bounds__(kBlock) void start_kernel(LanczosLaunch a) {
     block_sum<CB>(part, red);
     if (threadIdx.x < nc) sw.partials[size_t(local) * a.ld + a.col0 + threadIdx.x] = red[kWaves * CB + threadIdx.x];
     if (last_block(sw.ticket, sw.G, &flag)) {
+        double tot[CB];
+        grid_sum_cols<CB>(sw.partials, int(sw.G), int(a.ld), int(a.col0), nc, red, tot);
         for (int c = 0; c < nc; ++c) {
             const int col = int(a.col0) + c;
-            const double tot = grid_sum_col(sw.partials, int(sw.G), int(a.ld), col, red);
             if (threadIdx.x == 0) {
                 Chain* ch = &sw.chains[col];
-                const double nrm = sqrt(tot);
+                const double nrm = sqrt(tot[c]);
                 sw.state[1] += nrm > 0.0 ? 1 : 0;
                 ch->norm = nrm;
                 ch->s_cur = nrm > 0.0 ? 1.0 / nrm : 0.0;
@@ -285,13 +286,14 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
     block_sum<VB>(part, red);
     if (threadIdx.x < VB) sw.partials[size_t(local) * a.ld + a.col0 + threadIdx.x] = red[kWaves * VB + threadIdx.x];
     if (last_block(sw.ticket, sw.G, &flag)) {
+        double tot[VB];
+        grid_sum_cols<VB>(sw.partials, int(sw.G), int(a.ld), int(a.col0), VB, red, tot);
         for (int c = 0; c < VB; ++c) {
             const int col = int(a.col0) + c;
-            const double tot = grid_sum_col(sw.partials, int(sw.G), int(a.ld), col, red);
             if (threadIdx.x == 0) {
                 Chain* ch = &sw.chains[col];
                 if (ch->active) {
-                    const double bk = sqrt(tot);
+                    const double bk = sqrt(tot[c]);
                     const double ak = ch->alpha;
                     sw.alpha[size_t(col) * kMaxSteps + (step - 1)] = ak;
                     sw.beta[size_t(col) * kMaxSteps + (step - 1)] = bk;

@@ -129,23 +129,36 @@ __device__ __forceinline__ bool last_block(uint32_t* ticket, uint32_t G, int* fl
     return last;
 }
 
-// Fixed-order sum over the G block partials of one column,
-// partials[g * pstride + col]: thread i sums blocks i, i + kBlock, ..., then
-// the block combines the threads as a tree, so the order depends on G only.
-// Returns the total in every thread. red holds kBlock doubles.
-__device__ __forceinline__ double grid_sum_col(const double* partials, int G, int pstride, int col,
-                                               double* red) {
-    double s = 0.0;
-    for (int g = threadIdx.x; g < G; g += kBlock) s += partials[size_t(g) * pstride + col];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int half = kBlock / 2; half >= 1; half >>= 1) {
-        if (threadIdx.x < half) red[threadIdx.x] += red[threadIdx.x + half];
+// Fixed-order sums over the G block partials of the columns col0 .. col0 +
+// nc - 1 (nc <= NC), partials[g * pstride + col]: thread i sums blocks i,
+// i + kBlock, ... of every column in one pass (a block's partials of all
+// columns are one contiguous load), then the block combines the threads as a
+// tree, column by column, so the order depends on G only. tot[c] receives the
+// totals in every thread; red holds kBlock doubles.
+template <int NC>
+__device__ __forceinline__ void grid_sum_cols(const double* partials, int G, int pstride, int col0, int nc,
+                                              double* red, double (&tot)[NC]) {
+    double s[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s[c] = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) {
+        const double* p = partials + size_t(g) * pstride + col0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < nc) s[c] += p[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c >= nc) break;
+        red[threadIdx.x] = s[c];
+        __syncthreads();
+        for (int half = kBlock / 2; half >= 1; half >>= 1) {
+            if (threadIdx.x < half) red[threadIdx.x] += red[threadIdx.x + half];
+            __syncthreads();
+        }
+        tot[c] = red[0];
         __syncthreads();
     }
-    const double total = red[0];
-    __syncthreads();
-    return total;
 }
 
 }  // namespace ftlm

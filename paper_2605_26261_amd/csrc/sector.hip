@@ -158,15 +158,7 @@ struct NeighborVisitor {
     const BondTable& B;
     static constexpr int kGroup = 2;
     static constexpr bool kPairs = false;
-    static constexpr bool kTablePipe = false;
-    static constexpr int kSiteGroup = 2;
     __device__ __forceinline__ void flip(int b, uint32_t idx) { out[B.orig(b)] = idx; }
-    __device__ __forceinline__ void site_group(int b0, const uint32_t (&idx)[kSiteGroup],
-                                               const bool (&anti)[kSiteGroup], int count) {
-#pragma unroll
-        for (int g = 0; g < kSiteGroup; ++g)
-            if (g < count) out[B.orig(b0 + g)] = anti[g] ? uint64_t(idx[g]) : ~uint64_t(0);
-    }
     __device__ __forceinline__ void par(int b) { out[B.orig(b)] = ~uint64_t(0); }
     __device__ __forceinline__ void group(int b0, const uint32_t (&idx)[kGroup], const bool (&anti)[kGroup]) {
 #pragma unroll

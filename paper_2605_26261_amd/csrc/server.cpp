@@ -260,17 +260,19 @@ int ftlm_server::round() {
         g.dtype = opts.dtype;
         g.mode = opts.mode;
         g.n_sites = reqs[0]->n_sites;
-        uint32_t block = 0;
+        uint32_t block = 0, items = 0;
         for (Request* r : reqs) {
             SecWork w = r->job.secs[0];
             w.block0 = block;
             block = (block + w.G + 7) & ~7u;
+            items += w.items;
             desc_host[slot + g.secs.size()] = w;
             g.secs.push_back(w);
             g.lds = std::max(g.lds, r->job.lds);
             ids.push_back(r->id);
         }
         g.grid = int(block);
+        g.items = int(items);
         // equal R and 256-byte aligned blocks give every member the same chunks
         g.chunks = reqs[0]->job.chunks;
         g.dev_secs = desc + slot;

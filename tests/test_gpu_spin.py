@@ -12,7 +12,8 @@ against the general-spin oracle (oracle/spin.py):
   diagonalization of the dense Kronecker-product Hamiltonian at s = 1;
 * the spin-1 icosahedron FTLM over all M >= 0 sectors (R = 4, M = 40)
   against the oracle's FP64 run with the same start vectors
-  (tests/golden/icosahedron_s1.json).
+  (tests/golden/icosahedron_s1.json): FP64 to rounding, FP32 well inside
+  the oracle's spread over seeds.
 """
 import json
 import os
@@ -179,10 +180,22 @@ def test_icosahedron_s1_all_sectors_against_oracle(env, mode):
                     np.testing.assert_allclose(rec["beta"][r, :k], smp["beta"][:k], rtol=0, atol=1e-9)
                 else:
                     assert abs(rec["alpha"][r, 0] - smp["alpha"][0]) < 1e-5 * (1 + abs(smp["alpha"][0]))
+    # FP64 equals the oracle to rounding. FP32 vectors: after M = 40 steps the
+    # low levels of the large sectors are not converged, and the FP32 and FP64
+    # chains, which drift apart with the loss of orthogonality (Sec. 3.2),
+    # give slightly different quadratures there; an FP32-vector run of the
+    # oracle's own Lanczos shows the same 8.5e-4 of max |C| at T = 0.05. The
+    # bar is the paper's (Sec. 3.3): far below the stochastic error, here the
+    # oracle's sigma_emp over 10 further seeds at the same R = 4 (Eq. 22)
     for k in ("E", "C", "chi"):
         o = np.asarray(ref[k])
+        sig = np.asarray(ref["sigma"][k])
         scale = np.abs(o).max()
         assert np.max(np.abs(out[ftlm.F64][k] - o)) <= 1e-8 * scale, k
-        d32 = np.max(np.abs(out[ftlm.F32][k] - o))
-        print(f"mode {mode} {k}: FP32 max |d| = {d32:.2e} ({d32 / scale:.1e} of max)", flush=True)
-        assert d32 <= 1e-4 * scale, k
+        d32 = np.abs(out[ftlm.F32][k] - o)
+        where = sig >= 1e-3 * sig.max()
+        ratio = np.max(d32[where] / sig[where])
+        print(f"mode {mode} {k}: FP32 max |d| = {d32.max():.2e} ({d32.max() / scale:.1e} of max), "
+              f"max |d|/sigma_emp = {ratio:.1e}", flush=True)
+        assert d32.max() <= 2e-3 * scale, k
+        assert ratio <= 0.03, k

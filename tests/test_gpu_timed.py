@@ -15,7 +15,6 @@
   N = 34 workload against the oracle's first step.
 """
 import json
-import math
 import os
 
 import numpy as np
@@ -164,10 +163,15 @@ def test_ring34_four_chains_first_step(env):
     sec = ftlm.Sector(n, n_up, ftlm.CR)
     a, b, s = ftlm.lanczos(sec, g, ref["seed"], 0, 4, 2, ftlm.PM1, ftlm.F32)
     assert np.all(s == 2)
+    # +-1 entries are exact in FP32 and the sums over 2.3e9 rows run in FP64,
+    # but every row of H.x is summed in FP32 from terms of size up to
+    # sum|J|/2; that rounding does not average out (the diagonal of a row is
+    # the same FP32 sum for every row with the same bond pattern), so alpha_1
+    # carries a bias of a few units of 2^-24 sum|J|
+    tol_a = 2 * 2.0 ** -24 * sum(abs(J) for _, _, J in graphs.j1j2_ring(n, 1.0, ref["j2"]))
     for smp in ref["samples"]:
         r = smp["r"]
-        # +-1 entries are exact in FP32; the sums run over 2.3e9 rows in FP64
-        assert abs(a[r, 0] - smp["alpha"][0]) <= 1e-6 * math.fabs(smp["alpha"][0]) + 1e-6, (r, a[r, 0])
+        assert abs(a[r, 0] - smp["alpha"][0]) <= tol_a, (r, a[r, 0], tol_a)
         assert abs(b[r, 0] - smp["beta"][0]) <= 1e-6 * smp["beta"][0], (r, b[r, 0])
     del sec
     torch.cuda.empty_cache()
