@@ -305,18 +305,6 @@ __device__ __forceinline__ void finish_alpha(const SecWork& sw, const LanczosLau
     }
 }
 
-// Static-grid form (general-spin H.x, one block per slot): the block stores
-// its partials and the last block of the sector (ticket) sums them.
-template <int VB>
-__device__ __forceinline__ void alpha_tail(const SecWork& sw, const LanczosLaunch& a, const double* wsum,
-                                           double* red, uint32_t local, int* flag) {
-    store_partials<VB>(sw, a, wsum, local);
-    if (last_block(sw.ticket, sw.G, flag)) {
-        finish_alpha<VB>(sw, a, sw.G, red);
-        if (threadIdx.x == 0) *sw.ticket = 0u;
-    }
-}
-
 // First half of Lanczos step k over every sector of the launch (one sector,
 // all sectors of a plan, or a server round): w = H q_k - beta_{k-1} q_{k-1}
 // and the FP64 partials of <u_k, w>, summed in slot order into alpha_k (and

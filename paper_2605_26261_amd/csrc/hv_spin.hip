@@ -160,30 +160,47 @@ __global__ __launch_bounds__(kBlock) void hv_spin_kernel(SectorDev S, BondTable 
 }
 
 // First half of a Lanczos step over the sectors of the launch, as
-// hv_lanczos_kernel does it for spin 1/2.
+// hv_lanczos_kernel does it for spin 1/2: a persistent grid taking
+// (sector, item) pairs from the per-XCD queue, partials in per-item slots,
+// alpha summed by the last workgroup to leave.
 template <int MODE, typename T, int VB>
 __global__ __launch_bounds__(kBlock) void hv_spin_lanczos_kernel(LanczosLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int flag;
-    uint32_t local = 0;
-    const int s = sector_of_block(a.secs, a.nsec, blockIdx.x, &local);
-    if (s < 0) return;
-    const SecWork& sw = a.secs[s];
-    if (sw.state[1] == 0) return;
-    const int step = sw.state[0];
-    const SectorDev S = sw.S;
+    __shared__ uint32_t next;
     __shared__ BondTable B;
     __shared__ T ab[2 * VB];
-    stage_bonds(B, sw.bonds);
-    stage_epilogue<T, VB>(ab, sw.chains + a.col0);
-    const SpinLds l = spin_lds_setup<MODE>(smem, S);
-    double* wsum = l.red;
-    for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
-    __syncthreads();
-    const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
-    T* y = static_cast<T*>(sw.u[step & 1]);
-    hv_spin_body<MODE, T, VB, kEpiLanczos>(S, B, l, x, y, a.ld, a.col0, 0, S.dim, local, sw.G, ab, step == 1, wsum);
-    alpha_tail<VB>(sw, a, wsum, l.red, local, &flag);
+    const SecWork* secs = a.secs;
+    const uint32_t xcd = blockIdx.x & 7u;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(a.queue + xcd, 1u);
+        __syncthreads();
+        uint32_t local = 0;
+        const int s = queue_item(secs, a.nsec, xcd, next, &local);
+        __syncthreads();  // every thread has read `next`
+        if (s < 0) break;
+        const SecWork& sw = secs[s];
+        if (sw.state[1] == 0) continue;
+        const int step = sw.state[0];
+        const SectorDev S = sw.S;
+        stage_bonds(B, sw.bonds);
+        stage_epilogue<T, VB>(ab, sw.chains + a.col0);
+        const SpinLds l = spin_lds_setup<MODE>(smem, S);
+        double* wsum = l.red;
+        for (int i = threadIdx.x; i < kWaves * VB; i += kBlock) wsum[i] = 0.0;
+        __syncthreads();
+        const T* x = static_cast<const T*>(sw.u[(step - 1) & 1]);
+        T* y = static_cast<T*>(sw.u[step & 1]);
+        hv_spin_body<MODE, T, VB, kEpiLanczos>(S, B, l, x, y, a.ld, a.col0, 0, S.dim, local, sw.items, ab,
+                                               step == 1, wsum);
+        store_partials<VB>(sw, a, wsum, local);
+        __syncthreads();  // LDS (bonds, scalars, tables) is restaged by the next item
+    }
+    if (queue_exit(a.queue, gridDim.x, &flag)) {
+        double* red = reinterpret_cast<double*>(smem);
+        for (int s = 0; s < a.nsec; ++s)
+            if (secs[s].state[1] != 0) finish_alpha<VB>(secs[s], a, secs[s].items, red);
+    }
 }
 
 template <typename F>
@@ -358,9 +375,13 @@ hipError_t launch_hv_lanczos_spin(const LanczosLaunch& a, size_t lds, hipStream_
         constexpr int MODE = decltype(mm)::value;
         return with_spin_vb(a.vb, [&](auto vb) {
             auto kern = hv_spin_lanczos_kernel<MODE, T, decltype(vb)::value>;
+            if (!a.queue || a.items <= 0) return hipErrorInvalidValue;  // the queue counters are required
             hipError_t e = allow_lds(kern, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kern, dim3(unsigned(a.grid)), dim3(kBlock), lds, st, a);
+            int grid = 0;
+            e = persistent_grid(reinterpret_cast<const void*>(kern), lds, a.items, &grid);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kBlock), lds, st, a);
             return hipGetLastError();
         });
     };
