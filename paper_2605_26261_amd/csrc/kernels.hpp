@@ -227,11 +227,11 @@ __host__ __device__ inline uint32_t sector_items(uint32_t nrows) {
     return (g + 7) & ~7u;
 }
 
-// Work item k of XCD x in a persistent launch: the sectors' blocks whose
-// index inside the sector is x mod 8, sector by sector in launch order (a
-// block index keeps its XCD, so the tile order of for_each_tile still gives
-// each XCD its contiguous share). Returns the sector and *local, or -1 when
-// the XCD's items are exhausted.
+// Work item k of XCD x in a persistent launch: the sectors' items whose
+// index inside the sector is x mod 8, sector by sector in launch order (an
+// item index keeps its XCD, so for_each_tile still gives each XCD its own
+// super-tiles). Returns the sector and *local, or -1 when the XCD's items
+// are exhausted.
 __device__ __forceinline__ int queue_item(const SecWork* secs, int nsec, uint32_t xcd, uint32_t k,
                                           uint32_t* local) {
     for (int s = 0; s < nsec; ++s) {

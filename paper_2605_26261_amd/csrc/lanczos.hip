@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
             VU* lu = reinterpret_cast<VU*>(stage_u);
             VU* lw = reinterpret_cast<VU*>(stage_w);
             // A chunk is rows [h0, h0 + hr) of one tile; the block walks its
-            // tiles in for_each_tile's order. The next chunk's rows are loaded
+            // tiles in tile_span's order. The next chunk's rows are loaded
             // into registers while the current chunk is stored.
             VU pu[kPer], pw[kPer];
             auto tile_rows = [&](uint32_t tile) {
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(LanczosLaunch a) {
             }
         }
     }
-    for_each_tile(ntiles, local, sw.G, [&](uint32_t tile) {
+    for_each_span_tile(ntiles, local, sw.G, [&](uint32_t tile) {
         const uint32_t t = tile * kBlock + threadIdx.x;
         if constexpr (kStage) {
             if (staged) return;  // done above
