@@ -33,15 +33,19 @@ N_SITES, N_UP, R, M, SEED = 30, 15, 20, 100, 2
 # block widths of one FP32 Lanczos-epilogue H.x launch
 LAUNCH_WIDTHS_F32 = (1, 2, 4, 8, 10, 12, 16, 20, 32)
 
-# HBM bytes per steady-state launch of the dominant kernel (Lanczos-epilogue
-# H.x over a block of FP32 columns, per index map and block width), from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by the counts of a 2 GiB
-# copy (profiles/hv_lanczos_n30_r20_counters.md). They describe the kernel
-# sources with this hash and are dropped otherwise.
+# Bytes between the L2 and the memory side per steady-state launch of the
+# dominant kernel (Lanczos-epilogue H.x over a block of FP32 columns, per
+# index map and block width), from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
+# scaled by the counts of a 2 GiB copy and checked against request-size
+# counters (profiles/hv_lanczos_n30_r20_counters.md). The memory side
+# includes the Infinity Cache, so this bounds the HBM traffic from above.
+# They describe the kernel sources with this hash and are dropped otherwise.
 KERNEL_SOURCES = ["layout.hpp", "device.hpp", "kernels.hpp", "rowloop.hpp", "hv_impl.hpp", "hv_f32.hip"]
-MEASURED_TRAFFIC = {"sources": "c078a2c571d64cdc", "bytes": {
-    "clt": {1: 20.54e9, 2: 34.93e9, 4: 67.68e9, 8: 128.22e9, 10: 166.94e9, 12: 200.07e9, 16: 279.89e9, 20: 378.8e9},
-    "cr": {1: 12.83e9, 2: 26.93e9, 4: 55.24e9, 8: 117.09e9, 10: 155.24e9, 12: 192.96e9, 16: 250.5e9, 20: 318.03e9}}}
+MEASURED_TRAFFIC = {"sources": "98d279c6f5eea37f", "bytes": {
+    "clt": {1: 19.65e9, 2: 34.46e9, 4: 65.99e9, 8: 125.55e9, 10: 161.22e9, 12: 196.74e9, 16: 272.86e9, 20: 340.13e9},
+    "cr": {1: 13.43e9, 2: 26.96e9, 4: 54.97e9, 8: 117.52e9, 10: 153.98e9, 12: 191.06e9, 16: 267.93e9, 20: 337.47e9},
+    "full": {1: 99.64e9, 2: 112.51e9, 4: 148.28e9, 8: 210.72e9, 10: 252.98e9, 12: 287.15e9, 16: 369.13e9, 20: 433.36e9},
+    "lin": {1: 14.35e9, 2: 28.99e9, 4: 59.65e9, 8: 120.23e9, 10: 155.02e9, 12: 190.25e9, 16: 264.43e9, 20: 332.77e9}}}
 
 
 def kernel_source_hash():
@@ -684,7 +688,8 @@ def main():
         traffic = MEASURED_TRAFFIC["bytes"].get(best, {}).get(dom["batch"])
     roof = {"bound": "hbm", "achieved": dom["hv_alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom["hv_alg_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-            "traffic_unit": "bytes per launch (HBM fetch + write, counter-calibrated)",
+            "traffic_unit": "bytes per launch between L2 and the memory side (2 x FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated; includes Infinity Cache hits)",
             "kernel": f"hv_lanczos_kernel<uint32, {best.upper()}, float, {dom['batch']}> (Lanczos-epilogue H.x "
                       f"over {dom['batch']} FP32 columns)",
             "alg_bytes_per_launch": dom["hv_alg_bytes"], "avg_launch_ms": dom["hv_avg_ms"]}
