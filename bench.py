@@ -286,6 +286,8 @@ def serving(n_warm=200, n_meas=2000, rate=50.0, max_active=0, plain=True, steps_
             r = srv.poll(rid)
             if r is not None:
                 done[pending.pop(rid)] = r
+                if len(done) % 200 == 0:
+                    log(f"serving: {len(done)} of {len(reqs)} requests done")
         time.sleep(0.0005)
     stats = srv.stats()
     srv.close()
@@ -306,7 +308,9 @@ def serving(n_warm=200, n_meas=2000, rate=50.0, max_active=0, plain=True, steps_
     # FIFO latencies follow from the measured service times and the arrival
     # times, and are compared with the served latencies of the same requests
     service = []
-    for q in reqs[:n_warm + n_plain]:
+    for i, q in enumerate(reqs[:n_warm + n_plain]):
+        if i % 50 == 0:
+            log(f"plain FIFO: request {i} of {n_warm + n_plain}")
         t1 = time.perf_counter()
         driver.run(q["n_sites"], q["bonds"], [q["n_up"]], q["R"], q["M"], q["seed"], ftlm.PM1, batch=1, temps=temps)
         torch.cuda.synchronize()
@@ -425,6 +429,56 @@ def ghost_study(n_chains=8, M=100):
             "ghosts_f32": [int(x["ghost"].sum()) for x in res["f32"]],
             "ghosts_f64": [int(x["ghost"].sum()) for x in res["f64"]],
             "converged_clusters": n_conv, "max_cluster_weight_shift": dw}
+
+
+def general_spin(reps=3):
+    """General local spin (Sec. 2, Eqs. 11-17) on the icosahedron (N = 12,
+    30 bonds, J = 1), the M = 0 sectors of Table 1 at s = 2, 5/2 and 3
+    (digit sum A = N s): plain H.x at 1 and 8 FP32 columns with both index
+    maps (the compressed table only while d^N labels fit 32 bits, so not at
+    s = 3), and one Lanczos run of 8 Gaussian chains, M = 100 steps, in the
+    s = 5/2 sector. A state-bond counts each bond once per row (its two
+    ladder terms together)."""
+    import torch
+
+    from ftlm_inputs import graphs
+    from paper_2605_26261_amd import ftlm
+
+    n = 12
+    g = ftlm.Graph(n, graphs.icosahedron())
+    out = {"workload": "icosahedron N=12 (30 bonds, J=1), M=0 sectors of Table 1 at s=2, 5/2, 3; FP32"}
+    for two_s in (4, 5, 6):
+        a = n * two_s // 2
+        for name, mode in (("cr", ftlm.CR), ("clt", ftlm.CLT)):
+            if mode == ftlm.CLT and (two_s + 1) ** n > 2 ** 32:
+                continue
+            sec = ftlm.Sector(n, a, mode, two_s=two_s)
+            d = sec.dim
+            rec = {"dim": d}
+            for B in (1, 8):
+                x = torch.empty((d, B) if B > 1 else (d,), dtype=torch.float32, device="cuda").fill_(0.5)
+                y = torch.empty_like(x)
+                ms = timed_hv(ftlm, torch, sec, g, x, y, reps)
+                alg = 8 * d * B + (4 * d if name == "clt" else 0)
+                rec[f"hv_B{B}_ms"] = ms
+                rec[f"hv_B{B}_states_bonds_per_s"] = d * g.n_bonds * B / (ms * 1e-3)
+                rec[f"hv_B{B}_alg_gbs"] = alg / (ms * 1e-3) / 1e9
+                del x, y
+                torch.cuda.empty_cache()
+            if two_s == 5 and name == "cr":
+                ftlm.lanczos(sec, g, 3, 0, 8, 2, ftlm.GAUSS, ftlm.F32)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, st = ftlm.lanczos(sec, g, 3, 0, 8, 100, ftlm.GAUSS, ftlm.F32)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                rec["lanczos_R8_M100_s"] = dt
+                rec["lanczos_states_bonds_per_s"] = d * g.n_bonds * float(st.sum()) / dt
+            out[f"2s={two_s} {name}"] = rec
+            log("spin", two_s, name, json.dumps(rec))
+            del sec
+            torch.cuda.empty_cache()
+    return out
 
 
 def largest_sector():
@@ -663,14 +717,14 @@ def main():
                     help="index maps of the headline workload (compressed table, ranking, full table, Lin)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short kernel-only run for rocprofv3 counter passes")
-    ap.add_argument("--only", choices=["plan", "serving", "largest", "precision"],
+    ap.add_argument("--only", choices=["plan", "serving", "largest", "precision", "spin"],
                     help="run one secondary measurement alone and print its JSON (for kernel traces)")
     args = ap.parse_args()
     if args.profile_kernels:
         profile_kernels(None if args.batch == "auto" else int(args.batch))
         return
     if args.only:
-        run = {"plan": plan_vs_plain, "largest": largest_sector, "precision": precision,
+        run = {"plan": plan_vs_plain, "largest": largest_sector, "precision": precision, "spin": general_spin,
                "serving": lambda: serving(n_warm=200 if args.serve_requests >= 200 else 10,
                                           n_meas=args.serve_requests)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
@@ -741,6 +795,8 @@ def main():
         torch.cuda.empty_cache()
         out["precision"] = precision()
         log("precision", json.dumps(out["precision"]))
+        torch.cuda.empty_cache()
+        out["general_spin"] = general_spin()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
