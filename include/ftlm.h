@@ -241,7 +241,8 @@ int ftlm_lanczos_workspace_bytes(const ftlm_sector* s, int R, int dtype, size_t*
  * FP64 with a fixed reduction order (the result does not depend on which
  * other chains share the batch). Chain r stops after step k when k reaches
  * min(M, D) or beta_k <= eps * max_{j<=k}(|alpha_j|, beta_{j-1}), with eps =
- * 1e-6 (FP32) or 1e-12 (FP64). Outputs (host, synchronizes): alpha_host and
+ * 1e-4 (FP32: above the ~1e-5 round-off residual an FP32 chain leaves at an
+ * exact invariant subspace) or 1e-12 (FP64). Outputs (host, synchronizes): alpha_host and
  * beta_host [R][M] (row r holds chain r; entries past steps_host[r] are 0),
  * steps_host[R]. 1 <= R <= 64, 1 <= M <= 4096. A chain whose alpha_k or
  * beta_k comes out NaN or infinite stops at that step and the call returns

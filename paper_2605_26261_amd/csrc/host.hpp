@@ -153,7 +153,10 @@ struct LanczosJob {
         a.items = items;
         a.ld = uint64_t(R);
         a.dtype = dtype;
-        a.eps = dtype == FTLM_F32 ? 1e-6 : 1e-12;
+        // FP32 vectors: an exact invariant subspace leaves a residual of about
+        // 1e-5 of the coefficient scale (FP32 row sums and vector updates), so
+        // the threshold sits a factor 10 above it
+        a.eps = dtype == FTLM_F32 ? 1e-4 : 1e-12;
         a.mode = mode;
         a.n_sites = n_sites;
         a.two_s = two_s;
