@@ -35,6 +35,12 @@ def lib():
         L.spn_neighbors.argtypes = [i32, i32, vp, vp, vp, u64, u64, u64, vp]
         L.spn_offdiag_count.restype = u64
         L.spn_offdiag_count.argtypes = [i32, i32, i32, i32, vp, vp]
+        L.spn_rank_count.restype = None
+        L.spn_rank_count.argtypes = [i32, i32, i32, vp, u64, vp]
+        L.spn_unrank_count.restype = None
+        L.spn_unrank_count.argtypes = [i32, i32, i32, vp, u64, vp]
+        L.spn_hv_rows.restype = None
+        L.spn_hv_rows.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, u64, vp]
         L._spin_sigs = True
     return L
 
@@ -74,6 +80,35 @@ def hv(n_sites, two_s, bonds, x, basis_arr, row0=0, nrows=None):
     y = np.empty(nrows, dtype=np.float64)
     lib().spn_hv(n_sites, two_s, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), _ptr(basis_arr), d, _ptr(x), _ptr(y),
                  row0, nrows)
+    return y
+
+
+def rank_count(n_sites, two_s, a, labels):
+    """Indices of labels in the sector with digit sum a, by counting the
+    sector labels below each one (Eq. 15 dimensions; no stored basis)."""
+    labels = np.ascontiguousarray(np.atleast_1d(labels), dtype=np.uint64)
+    out = np.empty(labels.size, dtype=np.uint64)
+    lib().spn_rank_count(n_sites, two_s, a, _ptr(labels), labels.size, _ptr(out))
+    return out
+
+
+def unrank_count(n_sites, two_s, a, idx):
+    """Labels of sector indices (each < D), by counting."""
+    idx = np.ascontiguousarray(np.atleast_1d(idx), dtype=np.uint64)
+    out = np.empty(idx.size, dtype=np.uint64)
+    lib().spn_unrank_count(n_sites, two_s, a, _ptr(idx), idx.size, _ptr(out))
+    return out
+
+
+def hv_rows(n_sites, two_s, a, bonds, x, rows):
+    """FP64 rows `rows` of H x (x over the whole sector), labels and
+    partner indices found by counting, so that no basis is stored."""
+    bi, bj, J = _bonds(bonds)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    y = np.empty(rows.size, dtype=np.float64)
+    lib().spn_hv_rows(n_sites, two_s, a, len(bonds), _ptr(bi), _ptr(bj), _ptr(J), _ptr(x), _ptr(rows), rows.size,
+                      _ptr(y))
     return y
 
 

@@ -179,3 +179,108 @@ void spn_neighbors(int two_s, int n_bonds, const int32_t* bi, const int32_t* bj,
         }
     }
 }
+
+/* ---- ranks by counting (no stored basis) --------------------------------
+ * For sectors too large to enumerate in a test: the index of a label is the
+ * number of sector labels below it, counted with the dimensions D(m, A) of
+ * Eq. (15). Labels compare as integers, i.e. digit strings from the top
+ * digit down: a sector label y < x first differs from x at some digit k with
+ * y_k < x_k and equal digits above it, and its k lower digits are any string
+ * whose digit sum makes up the rest of A. */
+
+/* D(m, a) for m = 0..N and a = 0..N 2s, row m at t[m * (N 2s + 1)]. */
+static uint64_t* spn_dim_table(int n_sites, int two_s) {
+    const int w = n_sites * two_s + 1;
+    uint64_t* t = calloc((size_t)(n_sites + 1) * (size_t)w, sizeof(uint64_t));
+    t[0] = 1;
+    for (int m = 1; m <= n_sites; ++m)
+        for (int a = 0; a <= m * two_s; ++a) {
+            uint64_t c = 0;
+            for (int q = 0; q <= two_s && q <= a; ++q) c += t[(size_t)(m - 1) * w + (size_t)(a - q)];
+            t[(size_t)m * w + (size_t)a] = c;
+        }
+    return t;
+}
+
+static uint64_t dim_at(const uint64_t* t, int n_sites, int two_s, int m, int a) {
+    if (a < 0 || a > m * two_s) return 0;
+    return t[(size_t)m * (size_t)(n_sites * two_s + 1) + (size_t)a];
+}
+
+static uint64_t rank_count(const uint64_t* t, int n_sites, int two_s, int A, uint64_t x) {
+    const int d = two_s + 1;
+    if (x >= ipow((uint64_t)d, n_sites) || digit_sum(x, n_sites, d) != A) return SPN_NONE;
+    uint64_t idx = 0;
+    int rem = A;  /* digit sum left for digits k, k - 1, ..., 0 */
+    for (int k = n_sites - 1; k >= 0; --k) {
+        const int ak = digit(x, k, d);
+        for (int q = 0; q < ak; ++q) idx += dim_at(t, n_sites, two_s, k, rem - q);
+        rem -= ak;
+    }
+    return idx;
+}
+
+static uint64_t unrank_count(const uint64_t* t, int n_sites, int two_s, int A, uint64_t idx) {
+    const int d = two_s + 1;
+    uint64_t label = 0;
+    int rem = A;
+    for (int k = n_sites - 1; k >= 0; --k) {
+        int q = 0;
+        for (; q <= two_s; ++q) {
+            const uint64_t c = dim_at(t, n_sites, two_s, k, rem - q);
+            if (idx < c) break;
+            idx -= c;
+        }
+        label += (uint64_t)q * ipow((uint64_t)d, k);
+        rem -= q;
+    }
+    return label;
+}
+
+/* out[i] = index of labels[i] by counting (SPN_NONE outside the sector). */
+void spn_rank_count(int n_sites, int two_s, int A, const uint64_t* labels, uint64_t n, uint64_t* out) {
+    uint64_t* t = spn_dim_table(n_sites, two_s);
+    for (uint64_t i = 0; i < n; ++i) out[i] = rank_count(t, n_sites, two_s, A, labels[i]);
+    free(t);
+}
+
+/* out[i] = label of sector index idx[i] (idx[i] < D). */
+void spn_unrank_count(int n_sites, int two_s, int A, const uint64_t* idx, uint64_t n, uint64_t* out) {
+    uint64_t* t = spn_dim_table(n_sites, two_s);
+    for (uint64_t i = 0; i < n; ++i) out[i] = unrank_count(t, n_sites, two_s, A, idx[i]);
+    free(t);
+}
+
+/* y[i] = row rows[i] of H x (the sum of spn_hv, term for term in the same
+ * order), the row's label and its partners' indices found by counting. */
+void spn_hv_rows(int n_sites, int two_s, int A, int n_bonds, const int32_t* bi, const int32_t* bj,
+                 const double* J, const double* x, const uint64_t* rows, uint64_t count, double* y) {
+    const int d = two_s + 1;
+    const double s = 0.5 * two_s;
+    uint64_t* tab = spn_dim_table(n_sites, two_s);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < (int64_t)count; ++r) {
+        const uint64_t t = rows[r];
+        const uint64_t n = unrank_count(tab, n_sites, two_s, A, t);
+        double acc = 0.0, diag = 0.0;
+        for (int b = 0; b < n_bonds; ++b) {
+            const int i = bi[b], j = bj[b];
+            const int ai = digit(n, i, d), aj = digit(n, j, d);
+            const double mi = ai - s, mj = aj - s;
+            diag += J[b] * mi * mj;
+            const uint64_t di = ipow((uint64_t)d, i), dj = ipow((uint64_t)d, j);
+            if (ai >= 1 && aj <= two_s - 1) {
+                const double c = 0.5 * J[b] * ladder_up(two_s, mi - 1.0) * ladder_up(two_s, mj);
+                const uint64_t k = rank_count(tab, n_sites, two_s, A, n - di + dj);
+                if (k != SPN_NONE) acc += c * x[k];
+            }
+            if (ai <= two_s - 1 && aj >= 1) {
+                const double c = 0.5 * J[b] * ladder_up(two_s, mi) * ladder_up(two_s, mj - 1.0);
+                const uint64_t k = rank_count(tab, n_sites, two_s, A, n + di - dj);
+                if (k != SPN_NONE) acc += c * x[k];
+            }
+        }
+        y[r] = diag * x[t] + acc;
+    }
+    free(tab);
+}

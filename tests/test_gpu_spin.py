@@ -199,3 +199,61 @@ def test_icosahedron_s1_all_sectors_against_oracle(env, mode):
               f"max |d|/sigma_emp = {ratio:.1e}", flush=True)
         assert d32.max() <= 2e-3 * scale, k
         assert ratio <= 0.03, k
+
+
+# The general-spin sectors the benchmark times (icosahedron, M = 0 sectors of
+# Table 1 at s = 5/2, D = 144,840,476, and s = 3, D = 786,588,243; the
+# compressed table only where the d^N labels fit 32 bits), at both launch
+# widths it times. x holds the unnormalized +-1 start vectors of samples
+# 0..B-1 (exact in FP32); the oracle rebuilds columns 0 and B-1 in FP64 and
+# evaluates sampled rows with labels and partner indices found by counting
+# (Eq. 15 dimensions), so no basis of the sector is stored. Rows are read
+# back through contiguous windows.
+TIMED_SPIN = [(5, 0, 1), (5, 0, 8), (5, 1, 1), (5, 1, 8), (6, 1, 1), (6, 1, 8)]
+
+
+@pytest.mark.parametrize("two_s,mode,nvec", TIMED_SPIN)
+def test_table1_timed_sectors_sampled_rows(env, two_s, mode, nvec):
+    torch, ftlm, driver = env
+    n, seed, window = 12, 31, 1024
+    a = n * two_s // 2
+    bonds = graphs.icosahedron()
+    g = ftlm.Graph(n, bonds)
+    sec = ftlm.Sector(n, a, mode, two_s=two_s)
+    d = sec.dim
+    assert d == sp.dim(n, two_s, a)
+    work = torch.empty(ftlm.lanczos_workspace_bytes(sec, nvec, ftlm.F32), dtype=torch.uint8, device="cuda")
+    x = torch.empty((d, nvec) if nvec > 1 else (d,), dtype=torch.float32, device="cuda")
+    ftlm.start_vectors(sec, seed, 0, nvec, ftlm.PM1, x, work)
+    del work
+    y = torch.empty_like(x)
+    ftlm.hv(sec, g, x, y)
+    torch.cuda.synchronize()
+    del x
+    rng = np.random.default_rng(1000 * two_s + 10 * mode + nvec)
+    starts = sorted({0, d - window, *(int(v) for v in rng.integers(0, d - window, 10))})
+    rows, got = [], []
+    for s0 in starts:
+        w = y.narrow(0, s0, window).cpu().double().numpy().reshape(window, nvec)
+        pick = np.sort(rng.choice(window, 200, replace=False))
+        if s0 == d - window:
+            pick = np.union1d(pick, [window - 1])  # the last row
+        rows.append(s0 + pick)
+        got.append(w[pick])
+    rows = np.concatenate(rows).astype(np.uint64)
+    got = np.concatenate(got)
+    del y
+    torch.cuda.empty_cache()
+    for c in sorted({0, nvec - 1}):
+        xc = oracle.start_vector(seed, a, c, oracle.PM1, d, normalize=False)
+        want = sp.hv_rows(n, two_s, a, bonds, xc, rows)
+        del xc
+        diff = np.abs(got[:, c] - want)
+        rel = float(np.linalg.norm(got[:, c] - want) / np.linalg.norm(want))
+        print(f"2s={two_s} mode {mode} B={nvec} column {c}: {rows.size} rows, rel l2 {rel:.1e}, "
+              f"max |d| {diff.max():.1e}", flush=True)
+        # each row sums <= 2 N_B + 1 = 61 FP32 terms of size <= J s(s+1) from
+        # exact +-1 entries
+        assert rel <= 1e-6, (c, rel)
+        assert diff.max() <= 1e-4, (c, diff.max(), rows[diff.argmax()])
+    del sec

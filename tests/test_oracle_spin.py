@@ -181,3 +181,29 @@ def test_clt_over_base_d_labels():
                 assert prefix[blk] + bin(int(mask[blk]) & ((1 << j) - 1)).count("1") == want
             else:
                 assert want == sp.NONE
+
+
+@pytest.mark.parametrize("n,two_s", [(6, 2), (5, 3), (4, 6), (7, 1)])
+def test_counting_rank_equals_the_enumerated_basis(n, two_s):
+    # The counting rank (no stored basis) against binary search in the
+    # enumerated sector, over every label of [0, d^N) and every digit sum:
+    # equal indices in the sector, NONE outside it; unrank inverts it.
+    d = two_s + 1
+    labels = np.arange(d ** n, dtype=np.uint64)
+    for a in range(n * two_s + 1):
+        b = sp.basis(n, two_s, a)
+        want = np.full(d ** n, sp.NONE, dtype=np.uint64)
+        want[b.astype(np.int64)] = np.arange(b.size, dtype=np.uint64)
+        np.testing.assert_array_equal(sp.rank_count(n, two_s, a, labels), want)
+        np.testing.assert_array_equal(sp.unrank_count(n, two_s, a, np.arange(b.size)), b)
+
+
+@pytest.mark.parametrize("two_s,a", [(2, 12), (3, 18), (2, 15)])
+def test_sampled_rows_by_counting_equal_the_enumerated_hv(two_s, a):
+    # icosahedron sectors: rows picked at random, the first and the last row
+    bonds = graphs.icosahedron()
+    b = sp.basis(12, two_s, a)
+    x = np.random.default_rng(1).standard_normal(b.size)
+    rows = np.unique(np.concatenate([[0, b.size - 1], np.random.default_rng(2).choice(b.size, 300, replace=False)]))
+    y = sp.hv_rows(12, two_s, a, bonds, x, rows)
+    np.testing.assert_array_equal(y, sp.hv(12, two_s, bonds, x, b)[rows])
