@@ -132,6 +132,39 @@ def test_exact_trace_mode_equals_ed(env):
         np.testing.assert_allclose(got[key], want[key], rtol=1e-8, atol=1e-10)
 
 
+def _exact_trace_thermo(ftlm, driver, n, bonds, mode):
+    recs = []
+    g = ftlm.Graph(n, bonds)
+    for n_up in range((n + 1) // 2, n + 1):
+        sec = ftlm.Sector(n, n_up, mode)
+        d = sec.dim
+        parts = [driver.sector_samples(sec, g, min(64, d - r0), d + 2, 0, ftlm.UNIT, ftlm.F64, r0=r0)
+                 for r0 in range(0, d, 64)]
+        rec = {"n_up": n_up, "dim": d, "mult": driver.multiplicity(n, n_up)}
+        for k in ("theta", "weight", "steps"):
+            rec[k] = np.concatenate([p[k] for p in parts])
+        recs.append(rec)
+    return ftlm.thermo(n, recs, TEMPS, 1.0)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_site_relabelling_leaves_observables_unchanged(env, mode):
+    # The sector order, and so every index, depends on the site labels; the
+    # trace does not. Exact-trace FTLM of a random cluster and of the same
+    # cluster with its sites permuted agree to rounding.
+    torch, ftlm, driver = env
+    n = 9
+    rng = np.random.default_rng(12)
+    bonds = graphs.random_cluster(n, rng)
+    perm = rng.permutation(n)
+    moved = graphs.relabel(bonds, perm)
+    assert moved != bonds
+    a = _exact_trace_thermo(ftlm, driver, n, bonds, mode)
+    b = _exact_trace_thermo(ftlm, driver, n, moved, mode)
+    for key in ("E", "C", "chi", "lnZ"):
+        np.testing.assert_allclose(a[key], b[key], rtol=1e-9, atol=1e-11)
+
+
 def test_tiny_sectors_and_termination(env):
     torch, ftlm, driver = env
     n = 12
