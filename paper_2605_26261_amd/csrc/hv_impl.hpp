@@ -70,10 +70,15 @@ __device__ __forceinline__ T bond_coef(const BondTable& B, int b) {
 // never as an access outside x.
 template <typename T, int VB>
 struct GatherVisitor {
-    const T* __restrict__ x;
-    uint64_t ld;
-    uint32_t col0;
+    // Column col0 of row 0 of x as bytes, and the row stride in bytes (at
+    // most 64 columns of 8 bytes): a partner row's address is then one
+    // 32 x 32 -> 64-bit multiply-add.
+    const unsigned char* __restrict__ xb;
+    uint32_t ldb;
     uint32_t last;  // D - 1
+    __device__ __forceinline__ const T* row(uint32_t i) const {
+        return reinterpret_cast<const T*>(xb + uint64_t(i) * ldb);
+    }
     const BondTable& B;
     T (&acc)[VB];
     T& anti;
@@ -81,7 +86,7 @@ struct GatherVisitor {
         const T c = bond_coef<T>(B, b);
         T v[VB];
         idx = idx < last ? idx : last;
-        load_row<T, VB>(x + uint64_t(idx) * ld + col0, v);
+        load_row<T, VB>(row(idx), v);
 #pragma unroll
         for (int i = 0; i < VB; ++i) acc[i] += c * v[i];
         anti += c;
@@ -122,7 +127,7 @@ struct GatherVisitor {
         for (int g = 0; g < kSiteGroup; ++g) {
             const uint32_t c = idx[g] < last ? idx[g] : last;
             const uint32_t i = flips[g] ? c : 0u;
-            load_row<T, VB>(x + uint64_t(i) * ld + col0, slot[g]);
+            load_row<T, VB>(row(i), slot[g]);
             const T cb = bond_coef<T>(B, b0 + g);
             w[g] = flips[g] ? cb : T(0);
         }
@@ -153,7 +158,7 @@ struct GatherVisitor {
             for (int i = 0; i < VB; ++i) v[g][i] = T(0);
             if (flips[g]) {
                 const uint32_t i = idx[g] < last ? idx[g] : last;
-                load_row<T, VB>(x + uint64_t(i) * ld + col0, v[g]);
+                load_row<T, VB>(row(i), v[g]);
             }
         }
 #pragma unroll
@@ -211,7 +216,8 @@ __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, 
 #pragma unroll
             for (int c = 0; c < VB; ++c) acc[c] = T(0);
             T anti = T(0);
-            GatherVisitor<T, VB> vis{x, ld, col0, S.dim - 1, B, acc, anti};
+            GatherVisitor<T, VB> vis{reinterpret_cast<const unsigned char*>(x + col0), uint32_t(ld * sizeof(T)),
+                                     S.dim - 1, B, acc, anti};
             visit_row<L, MODE>(t, S.n_up, B, C, S.basis, table_map<MODE>(S), lds.ylds, vis);
             load_row<T, VB>(x + uint64_t(t) * ld + col0, xt);
             const T diag = jsum4 - anti;

@@ -63,9 +63,10 @@ __device__ __forceinline__ SpinLds spin_lds_setup(unsigned char* smem, const Sec
 // into [0, D) like the spin-1/2 visitor's.
 template <typename T, int VB>
 struct SpinGather {
-    const T* __restrict__ x;
-    uint64_t ld;
-    uint32_t col0;
+    // column col0 of row 0 of x as bytes and the row stride in bytes, as in
+    // the spin-1/2 visitor: one multiply-add per partner address
+    const unsigned char* __restrict__ xb;
+    uint32_t ldb;
     uint32_t last;
     const BondTable& B;
     T (&acc)[VB];
@@ -75,7 +76,7 @@ struct SpinGather {
         const T c = bond_coef<T>(B, b) * f;
         T v[VB];
         idx = idx < last ? idx : last;
-        load_row<T, VB>(x + uint64_t(idx) * ld + col0, v);
+        load_row<T, VB>(reinterpret_cast<const T*>(xb + uint64_t(idx) * ldb), v);
 #pragma unroll
         for (int i = 0; i < VB; ++i) acc[i] += c * v[i];
     }
@@ -120,7 +121,8 @@ __device__ __forceinline__ void hv_spin_body(const SectorDev& S, const BondTable
 #pragma unroll
             for (int c = 0; c < VB; ++c) acc[c] = T(0);
             T diag = T(0);
-            SpinGather<T, VB> vis{x, ld, col0, S.dim - 1, B, acc, diag};
+            SpinGather<T, VB> vis{reinterpret_cast<const unsigned char*>(x + col0), uint32_t(ld * sizeof(T)),
+                                  S.dim - 1, B, acc, diag};
             spin_row<MODE, T>(t, S, B, l, vis);
             load_row<T, VB>(x + uint64_t(t) * ld + col0, xt);
 #pragma unroll
