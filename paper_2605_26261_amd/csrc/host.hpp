@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -151,6 +152,7 @@ struct LanczosJob {
         a.nsec = nsec;
         a.grid = grid;
         a.items = items;
+        for (const SecWork& w : secs) a.max_dim = std::max<uint64_t>(a.max_dim, w.S.dim);
         a.ld = uint64_t(R);
         a.dtype = dtype;
         // FP32 vectors: an exact invariant subspace leaves a residual of about

@@ -390,9 +390,23 @@ hipError_t launch_hv_one(const SectorDev& s, const BondTable& B, const HvLaunch&
 // the number of work items.
 hipError_t persistent_grid(const void* kern, size_t lds, int items, int* grid);
 
+// Dynamic LDS of the Lanczos H.x that holds CR at 8 and 16 FP32 columns to
+// three workgroups per CU (their registers allow four) when the vector
+// block of the largest sector does not fit the 256 MB Infinity Cache: fewer
+// rows in flight keep more of the partner rows cached. N = 30 Lanczos step:
+// 8 columns 23.0 -> 22.2 ms, 16 columns 50.9 -> 47.0 ms; the same floor made
+// 10 and 12 columns and every CLT width slower.
+template <int MODE, typename T, int VB>
+size_t lanczos_lds_floor(uint64_t max_dim) {
+    const bool big = max_dim * uint64_t(VB) * sizeof(T) > (uint64_t(256) << 20);
+    return (MODE == kModeCr && sizeof(T) == 4 && (VB == 8 || VB == 16) && big) ? size_t(48) * 1024 : 0;
+}
+
 template <typename L, int MODE, typename T, int VB>
 hipError_t launch_lanczos_one(const LanczosLaunch& a, size_t lds, hipStream_t st) {
     auto kern = hv_lanczos_kernel<L, MODE, T, VB>;
+    const size_t floor = lanczos_lds_floor<MODE, T, VB>(a.max_dim);
+    if (lds < floor) lds = floor;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));

@@ -126,6 +126,7 @@ struct LanczosLaunch {
     int nsec;
     int grid;            // total blocks (sum of the sectors' G, 8-aligned)
     int items;           // work items of the persistent H.x (sum of the sectors' items)
+    uint64_t max_dim;    // the largest sector dimension (host launch tuning)
     uint64_t ld;
     uint32_t col0;
     int vb;
