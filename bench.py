@@ -41,11 +41,11 @@ LAUNCH_WIDTHS_F32 = (1, 2, 4, 8, 10, 12, 16, 20, 32)
 # includes the Infinity Cache, so this bounds the HBM traffic from above.
 # They describe the kernel sources with this hash and are dropped otherwise.
 KERNEL_SOURCES = ["layout.hpp", "device.hpp", "kernels.hpp", "rowloop.hpp", "hv_impl.hpp", "hv_f32.hip"]
-MEASURED_TRAFFIC = {"sources": "06412d67cf8b1c0c", "bytes": {
-    "clt": {1: 19.41e9, 2: 34.15e9, 4: 65.51e9, 8: 125.65e9, 10: 162.66e9, 12: 198.12e9, 16: 272.82e9, 20: 340.24e9},
-    "cr": {1: 13.46e9, 2: 26.81e9, 4: 54.75e9, 8: 117.36e9, 10: 153.08e9, 12: 189.74e9, 16: 269.17e9, 20: 337.55e9},
-    "full": {1: 99.53e9, 2: 111.78e9, 4: 148.0e9, 8: 210.28e9, 10: 253.41e9, 12: 287.72e9, 16: 368.11e9, 20: 432.62e9},
-    "lin": {1: 14.39e9, 2: 28.93e9, 4: 59.72e9, 8: 120.2e9, 10: 155.84e9, 12: 191.03e9, 16: 264.49e9, 20: 332.11e9}}}
+MEASURED_TRAFFIC = {"sources": "b2619466aa767ed5", "bytes": {
+    "clt": {1: 19.45e9, 2: 34.14e9, 4: 65.54e9, 8: 125.37e9, 10: 161.03e9, 12: 197.3e9, 16: 272.98e9, 20: 340.92e9},
+    "cr": {1: 13.43e9, 2: 26.78e9, 4: 54.56e9, 8: 112.29e9, 10: 153.15e9, 12: 190.33e9, 16: 251.09e9, 20: 336.95e9},
+    "full": {1: 99.57e9, 2: 112.04e9, 4: 148.21e9, 8: 210.32e9, 10: 253.28e9, 12: 287.36e9, 16: 367.29e9, 20: 432.79e9},
+    "lin": {1: 14.34e9, 2: 28.75e9, 4: 59.71e9, 8: 119.56e9, 10: 155.41e9, 12: 190.85e9, 16: 264.21e9, 20: 331.87e9}}}
 
 
 def kernel_source_hash():

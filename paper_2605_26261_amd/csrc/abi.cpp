@@ -466,8 +466,9 @@ struct TuneCache {
 // "_c3": the candidate set, cost model and kernel set; a cache file written
 // under an older one is not reused.
 std::string tune_key(const ftlm_sector* s, const ftlm_graph* g, int R, int dtype) {
-    std::string k = "N" + std::to_string(s->n_sites) + "_u" + std::to_string(s->n_up) + "_m" +
-                    std::to_string(s->mode) + "_t" + std::to_string(dtype) + "_R" + std::to_string(R) + "_c3_b";
+    std::string k = "N" + std::to_string(s->n_sites) + "_s" + std::to_string(s->two_s) + "_u" +
+                    std::to_string(s->n_up) + "_m" + std::to_string(s->mode) + "_t" + std::to_string(dtype) + "_R" +
+                    std::to_string(R) + "_c3_b";
     // the bond structure, so that two graphs with the same size do not share entries
     uint64_t h = 1469598103934665603ull;
     for (size_t b = 0; b < g->bi.size(); ++b) {
