@@ -286,3 +286,19 @@ def test_seed_spread_matches_oracle(ftlm):
         ftlm.seed_spread(np.zeros((0, 4)))
     import ctypes as ct
     assert ftlm._lib.ftlm_seed_spread(0, 4, None, None, None) == ftlm.E_INVALID
+
+
+def test_sector_size_limits(ftlm):
+    # indices are 32-bit in the kernels: a sector of 2^32 or more states is
+    # refused; the stored maps hold 32-bit labels, so they stop at N = 32;
+    # combinatorial ranking takes 64-bit labels up to N = 64
+    import math
+    assert math.comb(36, 18) >= 2 ** 32
+    for args in ((36, 18, ftlm.CR), (34, 17, ftlm.CLT), (33, 16, ftlm.FULL), (33, 16, ftlm.LIN)):
+        with pytest.raises(ftlm.FtlmError) as e:
+            ftlm.sector_table_bytes(*args)
+        assert e.value.code == ftlm.E_RANGE, args
+    assert ftlm.sector_table_bytes(34, 17, ftlm.CR) > 0
+    assert ftlm.sector_table_bytes(64, 1, ftlm.CR) > 0
+    # the full table at N = 32 holds one index per label of [0, 2^32)
+    assert ftlm.sector_table_bytes(32, 16, ftlm.FULL) >= 4 * 2 ** 32
