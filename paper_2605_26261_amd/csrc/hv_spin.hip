@@ -72,13 +72,83 @@ struct SpinGather {
     T (&acc)[VB];
     T& dsum;
     __device__ __forceinline__ void diag(int b, T mm) { dsum += T(2) * bond_coef<T>(B, b) * mm; }
+    __device__ __forceinline__ const T* row(uint32_t i) const {
+        return reinterpret_cast<const T*>(xb + uint64_t(i) * ldb);
+    }
     __device__ __forceinline__ void flip(int b, int, uint32_t idx, T f) {
         const T c = bond_coef<T>(B, b) * f;
         T v[VB];
         idx = idx < last ? idx : last;
-        load_row<T, VB>(reinterpret_cast<const T*>(xb + uint64_t(idx) * ldb), v);
+        load_row<T, VB>(row(idx), v);
 #pragma unroll
         for (int i = 0; i < VB; ++i) acc[i] += c * v[i];
+    }
+    // CR: two slots of one bond's two ladder terms in flight
+    // (spin_cr_row_pairs) at every width. Icosahedron s = 5/2, M = 0, one
+    // column: 12.9 -> 8.4 ms; s = 3, 8 columns: 186 -> 165 ms.
+    // CLT: the terms of kGroup bonds per group (spin_clt_row_groups); group
+    // sizes of 1 to 4 bonds timed at s = 5/2 (one column: 9.1, 8.0, 7.4 and
+    // 7.6 ms; 8 columns, Lanczos step: 30.3, 27.8, 26.3 and 26.7 ms; at 2 and
+    // 4 columns two bonds were best or within 3 %).
+    static constexpr bool kPairs = true;
+    static constexpr int kGroup = (VB == 1 || VB == 8) ? 3 : 2;
+    // The two slots: rows of x and their weights (J_b / 2 times the ladder
+    // factors for an existing term, else 0). A missing term loads row 0.
+    T slot_a[2][VB], slot_b[2][VB];
+    T w_a[2], w_b[2];
+    __device__ __forceinline__ void clear_slots() {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            w_a[g] = w_b[g] = T(0);
+#pragma unroll
+            for (int i = 0; i < VB; ++i) slot_a[g][i] = slot_b[g][i] = T(0);
+        }
+    }
+    __device__ __forceinline__ void load_slot(T (&slot)[2][VB], T (&w)[2], int b, const uint32_t (&idx)[2],
+                                              const bool (&on)[2], const T (&f)[2]) {
+        const T cb = bond_coef<T>(B, b);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const uint32_t c = idx[g] < last ? idx[g] : last;
+            load_row<T, VB>(row(on[g] ? c : 0u), slot[g]);
+            w[g] = on[g] ? cb * f[g] : T(0);
+        }
+    }
+    __device__ __forceinline__ void add_slot(const T (&slot)[2][VB], const T (&w)[2]) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+#pragma unroll
+            for (int i = 0; i < VB; ++i) acc[i] += w[g] * slot[g][i];
+        }
+    }
+    __device__ __forceinline__ void load_slot_a(int b, const uint32_t (&idx)[2], const bool (&on)[2],
+                                                const T (&f)[2]) {
+        load_slot(slot_a, w_a, b, idx, on, f);
+    }
+    __device__ __forceinline__ void load_slot_b(int b, const uint32_t (&idx)[2], const bool (&on)[2],
+                                                const T (&f)[2]) {
+        load_slot(slot_b, w_b, b, idx, on, f);
+    }
+    __device__ __forceinline__ void add_slot_a() { add_slot(slot_a, w_a); }
+    __device__ __forceinline__ void add_slot_b() { add_slot(slot_b, w_b); }
+    // kGroup bonds b0, b0 + 1, ...: term k is bond b0 + k / 2, e = +1 for
+    // even k; rows of the existing terms are loaded together, the others
+    // stay zero under weight zero.
+    __device__ __forceinline__ void group(int b0, const uint32_t (&idx)[2 * kGroup], const bool (&on)[2 * kGroup],
+                                          const T (&f)[2 * kGroup]) {
+        T v[2 * kGroup][VB];
+#pragma unroll
+        for (int k = 0; k < 2 * kGroup; ++k) {
+#pragma unroll
+            for (int i = 0; i < VB; ++i) v[k][i] = T(0);
+            if (on[k]) load_row<T, VB>(row(idx[k] < last ? idx[k] : last), v[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * kGroup; ++k) {
+            const T c = on[k] ? bond_coef<T>(B, b0 + k / 2) * f[k] : T(0);
+#pragma unroll
+            for (int i = 0; i < VB; ++i) acc[i] += c * v[k][i];
+        }
     }
 };
 
@@ -94,9 +164,12 @@ __device__ __forceinline__ void spin_row(uint32_t t, const SectorDev& S, const B
     const T* fu = ladder_factors<T>(l);
     if constexpr (MODE == kModeCr) {
         const CumDim D{l.table, S.bw, S.two_s + 1};
-        spin_cr_row<T>(t, S.n_up, S.two_s, B, D, fu, l.yp, l.ym, v);
+        if constexpr (V::kPairs) spin_cr_row_pairs<T>(t, S.n_up, S.two_s, B, D, fu, l.yp, l.ym, v);
+        else spin_cr_row<T>(t, S.n_up, S.two_s, B, D, fu, l.yp, l.ym, v);
     } else {
-        spin_clt_row<T>(t, S.two_s, B, S.basis, S.clt, l.table, fu, 1.0 / double(S.two_s + 1), v);
+        const double inv_d = 1.0 / double(S.two_s + 1);
+        if constexpr (V::kGroup > 0) spin_clt_row_groups<T>(t, S.two_s, B, S.basis, S.clt, l.table, fu, inv_d, v);
+        else spin_clt_row<T>(t, S.two_s, B, S.basis, S.clt, l.table, fu, inv_d, v);
     }
 }
 
@@ -332,6 +405,8 @@ __global__ __launch_bounds__(kThreads) void unrank_spin_kernel(SectorDev S, cons
 struct SpinNeighbors {
     uint64_t* out;
     const BondTable& B;
+    static constexpr bool kPairs = false;
+    static constexpr int kGroup = 0;  // one term at a time
     __device__ __forceinline__ void diag(int, float) {}
     __device__ __forceinline__ void flip(int b, int e, uint32_t idx, float) { out[2 * B.orig(b) + e] = idx; }
 };

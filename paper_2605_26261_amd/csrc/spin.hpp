@@ -160,6 +160,80 @@ __device__ __forceinline__ void spin_cr_row(uint32_t t, int a_tot, int two_s, co
     }
 }
 
+// spin_cr_row for a visitor that keeps two slots of row gathers in flight
+// (V::kPairs): the bonds, in their sorted order, go one at a time into slot A
+// and slot B in turn, each with its two ladder terms (e = +1, then -1), and
+// each slot is accumulated after the other slot's next loads are issued. A
+// term that does not exist is loaded from row 0 under weight zero, so every
+// lane loads and the compiler can wait for just the older slot. The top-down
+// pass over the sites runs ahead of the bonds only as far as the next bond's
+// lower site. The partner indices, the factors and the order of every
+// accumulation are those of spin_cr_row.
+template <typename T, typename V>
+__device__ __forceinline__ void spin_cr_row_pairs(uint32_t t, int a_tot, int two_s, const BondTable& B, CumDim D,
+                                                  const T* fu, uint32_t* yp, uint32_t* ym, V& v) {
+    uint64_t dig = 0;
+    uint32_t rem = t, Sp = 0, Sm = 0, Xp = 0, Xm = 0;
+    int A = a_tot, a = 0;
+    int p = B.n_sites - 1;  // the next site of the top-down pass
+    const T s = T(0.5) * T(two_s);
+    // runs the pass down to `lo`; a, Xp and Xm are then those of lo
+    auto advance = [&](int lo) {
+        for (; p >= lo; --p) {
+            int ap = 0;
+            for (int q = 1; q <= two_s; ++q)
+                if (D(p, A, q) <= rem) ap = q;
+            const uint32_t c0 = D(p, A, ap);
+            const uint32_t Tp = D(p, A + 1, ap) - c0, Tm = D(p, A - 1, ap) - c0;
+            const bool can_up = ap < two_s, can_dn = ap > 0;
+            Xp = (can_up ? D(p, A + 1, ap + 1) : 0u) - c0 + Sp;
+            Xm = (can_dn ? D(p, A - 1, ap - 1) : 0u) - c0 + Sm;
+            yp[p * 64] = (can_dn ? D(p, A, ap - 1) : 0u) - c0 - Sp - Tp;
+            ym[p * 64] = (can_up ? D(p, A, ap + 1) : 0u) - c0 - Sm - Tm;
+            dig |= uint64_t(ap) << (4 * p);
+            Sp += Tp;
+            Sm += Tm;
+            rem -= c0;
+            A -= ap;
+            a = ap;
+        }
+    };
+    // the diagonal term of bond b, and its two ladder terms: partner index,
+    // existence and single-site factor product
+    auto prepare = [&](int b, uint32_t (&idx)[2], bool (&on)[2], T (&f)[2]) {
+        advance(__builtin_amdgcn_readfirstlane(int(B.lo(b))));
+        const int hi = int(B.hi(b));
+        const int ah = digit_of(dig, hi);
+        v.diag(b, (T(a) - s) * (T(ah) - s));
+        on[0] = a < two_s && ah > 0;
+        on[1] = a > 0 && ah < two_s;
+        idx[0] = t + Xp + yp[hi * 64];
+        idx[1] = t + Xm + ym[hi * 64];
+        f[0] = on[0] ? fu[a] * fu[ah - 1] : T(0);
+        f[1] = on[1] ? fu[a - 1] * fu[ah] : T(0);
+    };
+    const int nb = B.n_bonds;
+    uint32_t idx[2];
+    bool on[2];
+    T f[2];
+    v.clear_slots();
+    int b = 0;
+    for (; b + 2 <= nb; b += 2) {
+        prepare(b, idx, on, f);
+        v.load_slot_a(b, idx, on, f);
+        v.add_slot_b();
+        prepare(b + 1, idx, on, f);
+        v.load_slot_b(b + 1, idx, on, f);
+        v.add_slot_a();
+    }
+    v.add_slot_b();
+    if (b < nb) {
+        prepare(b, idx, on, f);
+        v.load_slot_a(b, idx, on, f);
+        v.add_slot_a();
+    }
+}
+
 // The same row in compressed-lookup-table mode: the label comes from the
 // stored basis, its digits by division, and every partner label is the label
 // plus or minus d^lo - d^hi, looked up with Alg. 2. pw[p] = d^p (LDS).
@@ -175,6 +249,59 @@ __device__ __forceinline__ void spin_clt_row(uint32_t t, int two_s, const BondTa
         const int al = digit_of(dig, lo), ah = digit_of(dig, hi);
         v.diag(b, (T(al) - s) * (T(ah) - s));
         const uint32_t step = pw[lo] - pw[hi];  // d^lo - d^hi mod 2^32
+        if (al < two_s && ah > 0) v.flip(b, 0, clt_lookup(clt, n + step), fu[al] * fu[ah - 1]);
+        if (al > 0 && ah < two_s) v.flip(b, 1, clt_lookup(clt, n - step), fu[al - 1] * fu[ah]);
+    }
+}
+
+// spin_clt_row for a visitor that takes groups (V::kGroup > 0): the ladder
+// terms of kGroup consecutive bonds have their table loads in flight
+// together, then their row gathers (v.group); a term that does not exist
+// issues neither and is weighed by zero. A partner inside the sector always
+// finds its bit set in the table, so the index is prefix plus popcount.
+// Partner indices, factors and the order of the accumulations are those of
+// spin_clt_row.
+template <typename T, typename V>
+__device__ __forceinline__ void spin_clt_row_groups(uint32_t t, int two_s, const BondTable& B,
+                                                    const uint32_t* basis, const CltEntry* clt, const uint32_t* pw,
+                                                    const T* fu, double inv_d, V& v) {
+    constexpr int G = V::kGroup;
+    const uint32_t n = *gptr(basis + t);
+    const uint64_t dig = label_digits(n, B.n_sites, uint32_t(two_s + 1), inv_d);
+    const T s = T(0.5) * T(two_s);
+    int b = 0;
+    for (; b + G <= B.n_bonds; b += G) {
+        uint32_t m[2 * G], idx[2 * G];
+        bool on[2 * G];
+        T f[2 * G];
+        CltEntry e[2 * G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int lo = int(B.lo(b + g)), hi = int(B.hi(b + g));
+            const int al = digit_of(dig, lo), ah = digit_of(dig, hi);
+            v.diag(b + g, (T(al) - s) * (T(ah) - s));
+            const uint32_t step = pw[lo] - pw[hi];
+            on[2 * g] = al < two_s && ah > 0;
+            on[2 * g + 1] = al > 0 && ah < two_s;
+            m[2 * g] = n + step;
+            m[2 * g + 1] = n - step;
+            f[2 * g] = on[2 * g] ? fu[al] * fu[ah - 1] : T(0);
+            f[2 * g + 1] = on[2 * g + 1] ? fu[al - 1] * fu[ah] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * G; ++k) {
+            e[k] = CltEntry{0u, 0u};
+            if (on[k]) e[k] = clt_entry(clt, m[k] >> 5);
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * G; ++k) idx[k] = e[k].prefix + __popc(e[k].mask & ((1u << (m[k] & 31u)) - 1u));
+        v.group(b, idx, on, f);
+    }
+    for (; b < B.n_bonds; ++b) {
+        const int lo = int(B.lo(b)), hi = int(B.hi(b));
+        const int al = digit_of(dig, lo), ah = digit_of(dig, hi);
+        v.diag(b, (T(al) - s) * (T(ah) - s));
+        const uint32_t step = pw[lo] - pw[hi];
         if (al < two_s && ah > 0) v.flip(b, 0, clt_lookup(clt, n + step), fu[al] * fu[ah - 1]);
         if (al > 0 && ah < two_s) v.flip(b, 1, clt_lookup(clt, n - step), fu[al - 1] * fu[ah]);
     }

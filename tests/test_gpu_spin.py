@@ -120,6 +120,31 @@ def test_hv_against_oracle(env, n, two_s, a, mode):
                 assert rel <= tol, (dtype, nv, c, rel)
 
 
+@pytest.mark.parametrize("n,two_s,a", [(12, 2, 12), (8, 4, 16)])
+def test_index_maps_agree_bitwise(env, n, two_s, a):
+    """Both index maps visit a row's bonds in the same order with the same
+    ladder factors (the pipelined ranking pass and the grouped table lookups
+    alike), so their products must agree bit for bit at every width; widths
+    1 and 8 take groups of three bonds, the others groups of two, and 30 or
+    the random cluster's bond count leaves a ragged last group or none."""
+    torch, ftlm, _ = env
+    rng = np.random.default_rng(7 * n + a)
+    bonds = graphs.icosahedron() if n == 12 else graphs.random_cluster(n, rng)
+    g = ftlm.Graph(n, bonds)
+    cr = ftlm.Sector(n, a, ftlm.CR, two_s=two_s)
+    clt = ftlm.Sector(n, a, ftlm.CLT, two_s=two_s)
+    d = cr.dim
+    assert clt.dim == d and d % 256 != 0
+    for dtype in (torch.float32, torch.float64):
+        for nv in (1, 2, 4, 8):
+            x = torch.randn((d, nv) if nv > 1 else (d,), dtype=dtype, device="cuda")
+            y_cr = torch.empty_like(x)
+            y_clt = torch.empty_like(x)
+            ftlm.hv(cr, g, x, y_cr)
+            ftlm.hv(clt, g, x, y_clt)
+            np.testing.assert_array_equal(y_cr.cpu().numpy(), y_clt.cpu().numpy(), err_msg=f"{dtype} B={nv}")
+
+
 def test_exact_trace_ftlm_equals_ed(env):
     torch, ftlm, driver = env
     n, two_s = 5, 2
