@@ -68,7 +68,7 @@ __device__ __forceinline__ T bond_coef(const BondTable& B, int b) {
 // A partner index is in [0, D) by construction; it is clamped there anyway so
 // that a defect in the index arithmetic shows up as a parity failure and
 // never as an access outside x.
-template <typename T, int VB>
+template <typename T, int VB, int SG = 2>
 struct GatherVisitor {
     // Column col0 of row 0 of x as bytes, and the row stride in bytes (at
     // most 64 columns of 8 bytes): a partner row's address is then one
@@ -98,14 +98,15 @@ struct GatherVisitor {
     // (Lanczos step at N = 30): 8 at one column (9.0 -> 8.3 ms against 4),
     // 6 at 8 columns, 3 at 12, 2 from 16 up, 4 elsewhere.
     static constexpr int kGroup = VB == 1 ? 8 : VB == 8 ? 6 : VB == 12 ? 3 : VB >= 16 ? 2 : 4;
-    // CR: up to 8 columns, the bonds in slots of kSiteGroup with two slots in
-    // flight (cr_bonds_pairs); wider blocks take one bond at a time (flip /
+    // CR: up to 8 columns, the bonds in slots of kSiteGroup = SG (site_group,
+    // per width and epilogue) with two slots in flight (cr_bonds_pairs);
+    // wider blocks take one bond at a time (flip /
     // par). Lanczos step at N = 30: one column 15.1 -> 9.6 ms; from 10
     // columns up the two slots were slower (12 columns 36.6 -> 41.5 ms):
     // every lane then loads a full row per bond, parallel lanes included,
     // and the kernel is bound by the traffic, not the latency, of its gathers.
     static constexpr bool kPairs = VB <= 8;
-    static constexpr int kSiteGroup = 2;
+    static constexpr int kSiteGroup = SG;
     // The two slots: rows of x and their weights (J_b / 2 for a flip, else 0).
     // Every lane loads, so the loads are not under a branch and the compiler
     // can wait for exactly the older slot: a lane whose bond is parallel
@@ -197,6 +198,21 @@ __device__ __forceinline__ HvLds hv_lds_setup(unsigned char* smem, const SectorD
 // Lanczos epilogue y holds u_{k-1} on entry (unless `first`) and receives
 // w = hv_a (H u_k) - hv_b u_{k-1} per column (ab = [hv_a | hv_b], VB each); the products u_k[t] w[t] are
 // folded, tile by tile, into per-wave FP64 sums wsum[wave * VB + c] (LDS).
+// Bonds per slot of the two-slot CR pipeline, timed per width at N = 30 (FP32):
+//   1-2 columns: three bonds (plain H.x 7.95 -> 7.78 ms at one column, 8.26 ->
+//     7.97 at two; Lanczos step 9.74 -> 9.25 ms at two);
+//   4 columns: three in the Lanczos step (12.16 -> 11.78 ms), two in the plain
+//     H.x (9.6 against 9.7);
+//   8 columns: one in the plain H.x (19.9 -> 17.7 ms), two in the Lanczos step
+//     (one gave 23.6 ms against 22.0, three 22.5).
+// The slot size changes no partner index and no order of accumulation.
+constexpr int site_group(int vb, int epi) {
+    if (vb <= 2) return 3;
+    if (vb == 4) return epi == kEpiLanczos ? 3 : 2;
+    if (vb == 8) return epi == kEpiPlain ? 1 : 2;
+    return 2;
+}
+
 template <typename L, int MODE, typename T, int VB, int EPI>
 __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, const HvLds& lds,
                                         const T* __restrict__ x, T* __restrict__ y, uint64_t ld,
@@ -216,8 +232,8 @@ __device__ __forceinline__ void hv_body(const SectorDev& S, const BondTable& B, 
 #pragma unroll
             for (int c = 0; c < VB; ++c) acc[c] = T(0);
             T anti = T(0);
-            GatherVisitor<T, VB> vis{reinterpret_cast<const unsigned char*>(x + col0), uint32_t(ld * sizeof(T)),
-                                     S.dim - 1, B, acc, anti};
+            GatherVisitor<T, VB, site_group(VB, EPI)> vis{reinterpret_cast<const unsigned char*>(x + col0),
+                                                          uint32_t(ld * sizeof(T)), S.dim - 1, B, acc, anti};
             visit_row<L, MODE>(t, S.n_up, B, C, S.basis, table_map<MODE>(S), lds.ylds, vis);
             load_row<T, VB>(x + uint64_t(t) * ld + col0, xt);
             const T diag = jsum4 - anti;
