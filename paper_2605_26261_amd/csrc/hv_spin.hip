@@ -61,7 +61,7 @@ __device__ __forceinline__ SpinLds spin_lds_setup(unsigned char* smem, const Sec
 // Accumulates one row: the diagonal sum_b J_b m_lo m_hi and, per valid ladder
 // term, (J_b / 2) * f * x[partner] (Eqs. 12-14). Partner indices are clamped
 // into [0, D) like the spin-1/2 visitor's.
-template <typename T, int VB>
+template <typename T, int VB, int SB = 1>
 struct SpinGather {
     // column col0 of row 0 of x as bytes and the row stride in bytes, as in
     // the spin-1/2 visitor: one multiply-add per partner address
@@ -91,43 +91,47 @@ struct SpinGather {
     // 7.6 ms; 8 columns, Lanczos step: 30.3, 27.8, 26.3 and 26.7 ms; at 2 and
     // 4 columns two bonds were best or within 3 %).
     static constexpr bool kPairs = true;
+    static constexpr int kSlotBonds = SB;
     static constexpr int kGroup = (VB == 1 || VB == 8) ? 3 : 2;
-    // The two slots: rows of x and their weights (J_b / 2 times the ladder
-    // factors for an existing term, else 0). A missing term loads row 0.
-    T slot_a[2][VB], slot_b[2][VB];
-    T w_a[2], w_b[2];
+    // The two slots of kSlotBonds bonds: rows of x and their weights (J_b / 2
+    // times the ladder factors for an existing term, else 0); term k is bond
+    // b0 + k / 2. A missing term loads row 0.
+    static constexpr int kTerms = 2 * kSlotBonds;
+    T slot_a[kTerms][VB], slot_b[kTerms][VB];
+    T w_a[kTerms], w_b[kTerms];
     __device__ __forceinline__ void clear_slots() {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < kTerms; ++g) {
             w_a[g] = w_b[g] = T(0);
 #pragma unroll
             for (int i = 0; i < VB; ++i) slot_a[g][i] = slot_b[g][i] = T(0);
         }
     }
-    __device__ __forceinline__ void load_slot(T (&slot)[2][VB], T (&w)[2], int b, const uint32_t (&idx)[2],
-                                              const bool (&on)[2], const T (&f)[2]) {
-        const T cb = bond_coef<T>(B, b);
+    __device__ __forceinline__ void load_slot(T (&slot)[kTerms][VB], T (&w)[kTerms], int b0,
+                                              const uint32_t (&idx)[kTerms], const bool (&on)[kTerms],
+                                              const T (&f)[kTerms]) {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < kTerms; ++g) {
             const uint32_t c = idx[g] < last ? idx[g] : last;
             load_row<T, VB>(row(on[g] ? c : 0u), slot[g]);
+            const T cb = bond_coef<T>(B, b0 + g / 2);
             w[g] = on[g] ? cb * f[g] : T(0);
         }
     }
-    __device__ __forceinline__ void add_slot(const T (&slot)[2][VB], const T (&w)[2]) {
+    __device__ __forceinline__ void add_slot(const T (&slot)[kTerms][VB], const T (&w)[kTerms]) {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < kTerms; ++g) {
 #pragma unroll
             for (int i = 0; i < VB; ++i) acc[i] += w[g] * slot[g][i];
         }
     }
-    __device__ __forceinline__ void load_slot_a(int b, const uint32_t (&idx)[2], const bool (&on)[2],
-                                                const T (&f)[2]) {
-        load_slot(slot_a, w_a, b, idx, on, f);
+    __device__ __forceinline__ void load_slot_a(int b0, const uint32_t (&idx)[kTerms], const bool (&on)[kTerms],
+                                                const T (&f)[kTerms]) {
+        load_slot(slot_a, w_a, b0, idx, on, f);
     }
-    __device__ __forceinline__ void load_slot_b(int b, const uint32_t (&idx)[2], const bool (&on)[2],
-                                                const T (&f)[2]) {
-        load_slot(slot_b, w_b, b, idx, on, f);
+    __device__ __forceinline__ void load_slot_b(int b0, const uint32_t (&idx)[kTerms], const bool (&on)[kTerms],
+                                                const T (&f)[kTerms]) {
+        load_slot(slot_b, w_b, b0, idx, on, f);
     }
     __device__ __forceinline__ void add_slot_a() { add_slot(slot_a, w_a); }
     __device__ __forceinline__ void add_slot_b() { add_slot(slot_b, w_b); }
@@ -173,6 +177,11 @@ __device__ __forceinline__ void spin_row(uint32_t t, const SectorDev& S, const B
     }
 }
 
+// Bonds per slot of the two-slot CR pipeline (icosahedron, s = 5/2, M = 0):
+// two bonds took the 8-column Lanczos step from 25.7 to 23.8 ms but the plain
+// H.x at one column from 8.46 to 8.64 ms and at 8 columns from 22.9 to 23.9.
+constexpr int spin_slot_bonds(int vb, int epi) { return (vb == 8 && epi == kEpiLanczos) ? 2 : 1; }
+
 // Rows [row0, row0 + nrows) of y = H x (columns [col0, col0 + VB) of [D][ld]
 // blocks) over the tiles of block `bid` of a (sub-)grid of G blocks, with the
 // Lanczos epilogue of hv_body (w = hv_a H u_k - hv_b u_{k-1} and the FP64
@@ -194,8 +203,8 @@ __device__ __forceinline__ void hv_spin_body(const SectorDev& S, const BondTable
 #pragma unroll
             for (int c = 0; c < VB; ++c) acc[c] = T(0);
             T diag = T(0);
-            SpinGather<T, VB> vis{reinterpret_cast<const unsigned char*>(x + col0), uint32_t(ld * sizeof(T)),
-                                  S.dim - 1, B, acc, diag};
+            SpinGather<T, VB, spin_slot_bonds(VB, EPI)> vis{reinterpret_cast<const unsigned char*>(x + col0),
+                                                            uint32_t(ld * sizeof(T)), S.dim - 1, B, acc, diag};
             spin_row<MODE, T>(t, S, B, l, vis);
             load_row<T, VB>(x + uint64_t(t) * ld + col0, xt);
 #pragma unroll

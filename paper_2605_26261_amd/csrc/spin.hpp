@@ -161,11 +161,12 @@ __device__ __forceinline__ void spin_cr_row(uint32_t t, int a_tot, int two_s, co
 }
 
 // spin_cr_row for a visitor that keeps two slots of row gathers in flight
-// (V::kPairs): the bonds, in their sorted order, go one at a time into slot A
-// and slot B in turn, each with its two ladder terms (e = +1, then -1), and
-// each slot is accumulated after the other slot's next loads are issued. A
-// term that does not exist is loaded from row 0 under weight zero, so every
-// lane loads and the compiler can wait for just the older slot. The top-down
+// (V::kPairs): the bonds, in their sorted order, go V::kSlotBonds at a time
+// into slot A and slot B in turn, each with its two ladder terms (e = +1,
+// then -1), and each slot is accumulated after the other slot's next loads
+// are issued. A term that does not exist is loaded from row 0 under weight
+// zero, so every lane loads and the compiler can wait for just the older
+// slot. The last bonds (fewer than two slots) go one at a time. The top-down
 // pass over the sites runs ahead of the bonds only as far as the next bond's
 // lower site. The partner indices, the factors and the order of every
 // accumulation are those of spin_cr_row.
@@ -198,39 +199,42 @@ __device__ __forceinline__ void spin_cr_row_pairs(uint32_t t, int a_tot, int two
             a = ap;
         }
     };
-    // the diagonal term of bond b, and its two ladder terms: partner index,
-    // existence and single-site factor product
-    auto prepare = [&](int b, uint32_t (&idx)[2], bool (&on)[2], T (&f)[2]) {
+    // the diagonal term of bond b, and its two ladder terms (entries k and
+    // k + 1): partner index, existence and single-site factor product
+    constexpr int SB = V::kSlotBonds;
+    uint32_t idx[2 * SB];
+    bool on[2 * SB];
+    T f[2 * SB];
+    auto prepare = [&](int b, int k) {
         advance(__builtin_amdgcn_readfirstlane(int(B.lo(b))));
         const int hi = int(B.hi(b));
         const int ah = digit_of(dig, hi);
         v.diag(b, (T(a) - s) * (T(ah) - s));
-        on[0] = a < two_s && ah > 0;
-        on[1] = a > 0 && ah < two_s;
-        idx[0] = t + Xp + yp[hi * 64];
-        idx[1] = t + Xm + ym[hi * 64];
-        f[0] = on[0] ? fu[a] * fu[ah - 1] : T(0);
-        f[1] = on[1] ? fu[a - 1] * fu[ah] : T(0);
+        on[k] = a < two_s && ah > 0;
+        on[k + 1] = a > 0 && ah < two_s;
+        idx[k] = t + Xp + yp[hi * 64];
+        idx[k + 1] = t + Xm + ym[hi * 64];
+        f[k] = on[k] ? fu[a] * fu[ah - 1] : T(0);
+        f[k + 1] = on[k + 1] ? fu[a - 1] * fu[ah] : T(0);
     };
     const int nb = B.n_bonds;
-    uint32_t idx[2];
-    bool on[2];
-    T f[2];
     v.clear_slots();
     int b = 0;
-    for (; b + 2 <= nb; b += 2) {
-        prepare(b, idx, on, f);
+    for (; b + 2 * SB <= nb; b += 2 * SB) {
+#pragma unroll
+        for (int g = 0; g < SB; ++g) prepare(b + g, 2 * g);
         v.load_slot_a(b, idx, on, f);
         v.add_slot_b();
-        prepare(b + 1, idx, on, f);
-        v.load_slot_b(b + 1, idx, on, f);
+#pragma unroll
+        for (int g = 0; g < SB; ++g) prepare(b + SB + g, 2 * g);
+        v.load_slot_b(b + SB, idx, on, f);
         v.add_slot_a();
     }
     v.add_slot_b();
-    if (b < nb) {
-        prepare(b, idx, on, f);
-        v.load_slot_a(b, idx, on, f);
-        v.add_slot_a();
+    for (; b < nb; ++b) {
+        prepare(b, 0);
+        if (on[0]) v.flip(b, 0, idx[0], f[0]);
+        if (on[1]) v.flip(b, 1, idx[1], f[1]);
     }
 }
 
