@@ -114,7 +114,7 @@ size_t layout_state(uint64_t dim, int R, int dtype, size_t off, SectorState& st)
     const size_t es = dtype == FTLM_F32 ? 4 : 8;
     st.u0 = off; off = align256(off + size_t(dim) * size_t(R) * es);
     st.u1 = off; off = align256(off + size_t(dim) * size_t(R) * es);
-    const size_t slots = std::max(rows_grid(uint32_t(dim)), sector_items(uint32_t(dim)));
+    const size_t slots = std::max(stream_grid(uint32_t(dim)), sector_items(uint32_t(dim)));
     st.partials = off; off = align256(off + slots * size_t(R) * sizeof(double));
     st.chains = off; off = align256(off + size_t(R) * sizeof(Chain));
     st.alpha = off; off = align256(off + size_t(R) * kMaxSteps * sizeof(double));
@@ -130,7 +130,7 @@ size_t layout_state(uint64_t dim, int R, int dtype, size_t off, SectorState& st)
 // Fills job.secs for sectors whose tables are described by `devs` and whose
 // state sits at `states` inside `base`. Each graph contributes its bond table
 // in the caller's labels. The descriptor array goes to `dev_secs`
-// (device). Blocks of the static-grid kernels: each sector gets rows_grid(D)
+// (device). Blocks of the static-grid kernels: each sector gets stream_grid(D)
 // blocks starting at a multiple of 8; the persistent H.x splits it into
 // sector_items(D) work items.
 void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::vector<SectorState>& states,
@@ -172,7 +172,7 @@ void job_layout(LanczosJob& job, const std::vector<SectorDev>& devs, const std::
         w.beta = at<double>(base, st.beta);
         w.keys = at<uint64_t>(base, st.keys);
         job.key_ptrs.push_back(at<uint64_t>(base, st.keys));
-        w.G = rows_grid(devs[i].dim);
+        w.G = stream_grid(devs[i].dim);
         w.items = sector_items(devs[i].dim);
         items += w.items;
         w.block0 = block;

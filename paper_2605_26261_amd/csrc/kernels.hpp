@@ -95,10 +95,10 @@ struct HvLaunch {
 
 // One sector of a Lanczos launch (one sector, all sectors of a plan, or the
 // active requests of a server round), in device memory. In the kernels with a
-// static grid (start vectors, update, general-spin H.x) its blocks are
-// [block0, block0 + G) of the launch grid, with G = rows_grid(D); the
-// persistent spin-1/2 H.x splits it into `items` = sector_items(D) work
-// items. Both depend on D only, and so does the reduction order of every
+// static grid (start vectors, update) its blocks are [block0, block0 + G) of
+// the launch grid, with G = stream_grid(D); the persistent Lanczos H.x
+// kernels (spin 1/2 and general spin) split it into `items` =
+// sector_items(D) work items. Both depend on D only, and so does the reduction order of every
 // column. Each sector carries its own bond table and step counter, so
 // sectors of different graphs at different Lanczos steps can share a launch.
 struct SecWork {
@@ -201,16 +201,25 @@ __host__ __device__ inline size_t hv_lds_bytes(const SectorDev& s) {
 }
 
 
-// Grid of the persistent row kernels for a row count: a multiple of 8 (one
-// share per XCD) capped near the number of resident workgroups, so reduction
-// partials depend on the row count only.
-__host__ __device__ inline uint32_t rows_grid(uint32_t nrows) {
+// Grid of a row kernel for a row count: a multiple of 8 (one share per XCD)
+// and at most `cap` blocks, so reduction partials depend on the row count
+// only.
+__host__ __device__ inline uint32_t capped_grid(uint32_t nrows, uint32_t cap) {
     const uint32_t tiles = (nrows + kBlock - 1) / kBlock;
     if (tiles < 8) return tiles == 0 ? 1u : tiles;
-    const uint32_t cap = 2048;
     const uint32_t g = tiles < cap ? tiles : cap;
     return (g + 7) & ~7u;
 }
+
+// The plain H.x: near the number of resident workgroups (latency-bound
+// gathers need every slot).
+__host__ __device__ inline uint32_t rows_grid(uint32_t nrows) { return capped_grid(nrows, 2048); }
+
+// The streaming start and update kernels: 512 blocks, two per CU. N = 30,
+// 20 chains as 8 + 8 + 4 columns: 55.7 ms per Lanczos step of all three
+// blocks with 2048 blocks, 55.0 with 1024 or 768, 54.3-54.7 with 512, 55.4
+// with 384 and 55.9 with 256 (one column alone was 2 % slower at 512).
+__host__ __device__ inline uint32_t stream_grid(uint32_t nrows) { return capped_grid(nrows, 512); }
 
 // Work items of a sector in the persistent Lanczos H.x, each with its own
 // slot of reduction partials: a multiple of 8 (an equal count per XCD), about
