@@ -179,6 +179,39 @@ def test_exact_trace_ftlm_equals_ed(env):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_chains_same_at_every_launch_width(env, mode):
+    """A chain's alpha and beta do not depend on the launch width: every
+    column's row terms, epilogue and FP64 sums are taken in the same order
+    whether the chain runs alone or with seven others, although the
+    8-column Lanczos kernel takes two bonds per ranking slot in CR mode and
+    the 1-column one takes one. Chains 0..3 of the 8-chain FP64 run also
+    match the oracle's first steps (golden, M = 0 sector of the spin-1
+    icosahedron, D = 73,789: many row tiles, 30 bonds)."""
+    torch, ftlm, _ = env
+    ref = json.load(open(os.path.join(GOLDEN, "icosahedron_s1.json")))
+    n, two_s, M, seed = ref["n_sites"], ref["two_s"], ref["M"], ref["seed"]
+    assert ref["dist"] == "pm1"
+    g = ftlm.Graph(n, [tuple(b) for b in ref["bonds"]])
+    sref = ref["sectors"][0]
+    sec = ftlm.Sector(n, sref["a"], mode, two_s=two_s)
+    assert sec.dim == sref["dim"] == 73789
+    for dtype in (ftlm.F64, ftlm.F32):
+        a8, b8, s8 = ftlm.lanczos(sec, g, seed, 0, 8, M, ftlm.PM1, dtype)
+        for r0, w in ((0, 1), (3, 1), (7, 1), (2, 4), (5, 2)):
+            a, b, st = ftlm.lanczos(sec, g, seed, r0, w, M, ftlm.PM1, dtype)
+            np.testing.assert_array_equal(st, s8[r0:r0 + w])
+            np.testing.assert_array_equal(a, a8[r0:r0 + w], err_msg=f"dtype {dtype} chains {r0}..{r0 + w - 1}")
+            np.testing.assert_array_equal(b, b8[r0:r0 + w], err_msg=f"dtype {dtype} chains {r0}..{r0 + w - 1}")
+        if dtype == ftlm.F64:
+            for smp in sref["samples"]:
+                r = smp["r"]
+                k = min(10, smp["steps"])
+                assert s8[r] == smp["steps"]
+                np.testing.assert_allclose(a8[r, :k], smp["alpha"][:k], rtol=0, atol=1e-9)
+                np.testing.assert_allclose(b8[r, :k], smp["beta"][:k], rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_icosahedron_s1_all_sectors_against_oracle(env, mode):
     torch, ftlm, driver = env
     path = os.path.join(GOLDEN, "icosahedron_s1.json")
