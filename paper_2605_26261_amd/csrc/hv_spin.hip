@@ -83,9 +83,10 @@ struct SpinGather {
 #pragma unroll
         for (int i = 0; i < VB; ++i) acc[i] += c * v[i];
     }
-    // CR: two slots of one bond's two ladder terms in flight
-    // (spin_cr_row_pairs) at every width. Icosahedron s = 5/2, M = 0, one
-    // column: 12.9 -> 8.4 ms; s = 3, 8 columns: 186 -> 165 ms.
+    // CR: two slots, each with the ladder terms of SB bonds, in flight
+    // (spin_cr_row_pairs) at every width (SB = spin_slot_bonds). Against one
+    // flip at a time, icosahedron M = 0: s = 5/2, one column 12.9 -> 8.4 ms;
+    // s = 3, 8 columns 186 -> 165 ms.
     // CLT: the terms of kGroup bonds per group (spin_clt_row_groups); group
     // sizes of 1 to 4 bonds timed at s = 5/2 (one column: 9.1, 8.0, 7.4 and
     // 7.6 ms; 8 columns, Lanczos step: 30.3, 27.8, 26.3 and 26.7 ms; at 2 and
