@@ -250,6 +250,34 @@ def test_hv_rows_shard(env):
         assert torch.equal(part, y[row0:row0 + nrows])
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_single_vector_buffer_gathers_bitwise(env, mode):
+    """A single contiguous vector is gathered through a buffer resource with
+    32-bit offsets, a column of a wider block through pointers: the products
+    must agree bit for bit (same partner rows, same order), in full and in
+    row windows (ftlm_hv_rows), FP32 and FP64. J1-J2 4x6 lattice, S^z = 1:
+    D = 2,496,144, 9751 row tiles with a ragged last one."""
+    torch, ftlm = env
+    n, n_up = 24, 13
+    g = ftlm.Graph(n, graphs.square_j1j2())
+    sec = ftlm.Sector(n, n_up, mode)
+    d = sec.dim
+    assert d == math.comb(24, 13) and d % 256 != 0
+    gen = torch.Generator(device="cuda").manual_seed(11 + mode)
+    for dtype in (torch.float32, torch.float64):
+        x2 = torch.randn(d, 2, dtype=dtype, device="cuda", generator=gen)
+        x = x2[:, 1].contiguous()
+        y2 = torch.empty_like(x2)
+        y = torch.empty_like(x)
+        ftlm.hv(sec, g, x2, y2)
+        ftlm.hv(sec, g, x, y)
+        assert torch.equal(y, y2[:, 1]), dtype
+        for row0, nrows in [(0, 777), (123457, 50001), (d - 333, 333)]:
+            part = torch.empty(nrows, dtype=dtype, device="cuda")
+            ftlm.hv_rows(sec, g, x, part, row0, nrows)
+            assert torch.equal(part, y[row0:row0 + nrows]), (dtype, row0)
+
+
 def test_hv_deterministic(env):
     torch, ftlm = env
     n, n_up = 24, 12
