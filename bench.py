@@ -41,11 +41,11 @@ LAUNCH_WIDTHS_F32 = (1, 2, 4, 8, 10, 12, 16, 20, 32)
 # includes the Infinity Cache, so this bounds the HBM traffic from above.
 # They describe the kernel sources with this hash and are dropped otherwise.
 KERNEL_SOURCES = ["layout.hpp", "device.hpp", "kernels.hpp", "rowloop.hpp", "hv_impl.hpp", "hv_f32.hip"]
-MEASURED_TRAFFIC = {"sources": "f96abbddc54322b8", "bytes": {
-    "clt": {1: 19.47e9, 2: 34.22e9, 4: 65.78e9, 8: 125.85e9, 10: 161.08e9, 12: 197.42e9, 16: 272.61e9, 20: 339.96e9},
-    "cr": {1: 13.41e9, 2: 26.85e9, 4: 55.81e9, 8: 112.98e9, 10: 153.11e9, 12: 190.11e9, 16: 251.13e9, 20: 337.83e9},
-    "full": {1: 99.67e9, 2: 111.91e9, 4: 148.26e9, 8: 210.78e9, 10: 252.95e9, 12: 286.81e9, 16: 368.09e9, 20: 433.36e9},
-    "lin": {1: 14.35e9, 2: 28.76e9, 4: 59.7e9, 8: 119.98e9, 10: 155.9e9, 12: 190.49e9, 16: 264.56e9, 20: 332.35e9}}}
+MEASURED_TRAFFIC = {"sources": "1123cd4f9861cbbe", "bytes": {
+    "clt": {1: 19.44e9, 2: 34.19e9, 4: 65.48e9, 8: 125.77e9, 10: 160.94e9, 12: 197.3e9, 16: 272.91e9, 20: 340.19e9},
+    "cr": {1: 13.41e9, 2: 26.88e9, 4: 55.84e9, 8: 112.51e9, 10: 153.01e9, 12: 190.25e9, 16: 250.94e9, 20: 338.26e9},
+    "full": {1: 99.57e9, 2: 111.91e9, 4: 147.91e9, 8: 210.6e9, 10: 253.37e9, 12: 286.72e9, 16: 367.8e9, 20: 433.01e9},
+    "lin": {1: 14.4e9, 2: 28.82e9, 4: 59.68e9, 8: 119.64e9, 10: 155.34e9, 12: 190.45e9, 16: 264.38e9, 20: 332.48e9}}}
 
 
 def kernel_source_hash():
