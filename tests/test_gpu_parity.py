@@ -314,6 +314,51 @@ def test_start_vectors_match_oracle(env, dist, dtype):
         assert abs(norms[c] - math.sqrt(float(np.dot(got[:, c], got[:, c])))) <= 1e-12 * norms[c]
 
 
+def test_hv_n32_single_vector_high_offsets(env):
+    # One FP32 vector of the J1-J2 ring N = 32 (J2 = 0.3), S^z = 0: D =
+    # 601,080,390 rows, 2.4 GB, so the buffer-resource gathers of a single
+    # vector take byte offsets up to 2.4e9, past 2^31. Rows on both sides of
+    # row 2^29 (byte offset 2^31) and the last rows are checked against the
+    # oracle, and bit for bit against a column of a two-column block (pointer
+    # gathers).
+    torch, ftlm = env
+    n, n_up = 32, 16
+    bonds = graphs.j1j2_ring(n, 1.0, 0.3)
+    g = ftlm.Graph(n, bonds)
+    sec = ftlm.Sector(n, n_up, ftlm.CR)
+    d = sec.dim
+    assert d == math.comb(32, 16) and d * 4 > 2 ** 31
+    work = torch.empty(ftlm.lanczos_workspace_bytes(sec, 1, ftlm.F32), dtype=torch.uint8, device="cuda")
+    x = torch.empty(d, dtype=torch.float32, device="cuda")
+    ftlm.start_vectors(sec, 7, 0, 1, ftlm.PM1, x, work)
+    del work
+    y = torch.empty_like(x)
+    ftlm.hv(sec, g, x, y)
+    x2 = torch.empty(d, 2, dtype=torch.float32, device="cuda")
+    x2[:, 0].copy_(x)
+    x2[:, 1].copy_(x)
+    y2 = torch.empty_like(x2)
+    ftlm.hv(sec, g, x2, y2)
+    del x, x2
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(32)
+    starts = sorted(set([0, 2 ** 29 - 512, 2 ** 29 + 256, d - 1024] +
+                        [int(v) for v in rng.integers(0, d - 1024, 12)]))
+    rows, got = [], []
+    for a in starts:
+        w = y.narrow(0, a, 1024)
+        assert torch.equal(w, y2.narrow(0, a, 1024)[:, 0]), a
+        w = w.cpu().double().numpy()
+        pick = np.unique(rng.integers(0, 1024, 64))
+        rows.append(a + pick)
+        got.append(w[pick])
+    rows = np.concatenate(rows).astype(np.uint64)
+    got = np.concatenate(got)
+    want = oracle.hv_rows_stream(n, n_up, bonds, 7, 0, oracle.PM1, rows)
+    assert _rel_l2(got, want) <= 1e-6
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-5)
+
+
 def test_hv_n34_rows_sampled(env):
     # The largest single sector: J1-J2 ring N = 34 (J1 = 1, J2 = 0.3, 68 bonds),
     # S^z = 0, D = 2,333,606,220 > 2^31, combinatorial ranking only. x is the
